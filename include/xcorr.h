@@ -1,0 +1,170 @@
+/*
+ * xcorr.h -- C ABI of the MI355X X-engine.
+ *
+ * The X-engine of an FX correlator (Clark, La Plante and Greenhill, Sec. 2.1): for every
+ * frequency channel f it integrates over time the outer product of the vector of station
+ * signals with itself (Eq. 4), keeping only the lower triangle of the Hermitian result
+ * (the Hermitian restriction stated after Eq. 4), with both polarisations of every station
+ * in the vector:
+ *
+ *   V[f][s1*(s1+1)/2 + s2][p*npol + q] = sum_t x[t][f][s1][p] * conj(x[t][f][s2][q]),
+ *   for 0 <= s2 <= s1 < nstation, 0 <= p, q < npol.
+ *
+ * Both cross-polarisation slots of an autocorrelation (s1 == s2, p != q) are stored; the
+ * slot with p < q equals the conjugate of the slot with p > q.
+ *
+ * Layouts (all row-major, no padding):
+ *   input   x[ntime][nchan][nstation][npol] complex samples, the corner-turned order of
+ *           Sec. 4.1 (station fastest, then channel, then time);
+ *   output  V[nchan][nstation*(nstation+1)/2][npol*npol] complex values, interleaved
+ *           (real, imaginary), the packed correlation matrix of Algorithm 1 (Sec. 5).
+ *
+ * Sample formats (xcorr_in_dtype):
+ *   XCORR_IN_CI8   2 bytes per sample: int8 real, int8 imaginary.
+ *   XCORR_IN_CI4   1 byte per sample: real part in the high nibble, imaginary part in the
+ *                  low nibble, each a two's complement integer in [-8, 7].
+ *   XCORR_IN_CF32  8 bytes per sample: float real, float imaginary (F32_CMAC only).
+ *   Integer samples are used as raw integers (no normalisation), so integer visibilities
+ *   are exact integers.
+ *
+ * Arithmetic paths (xcorr_acc_dtype):
+ *   XCORR_ACC_F32_CMAC        the paper's method: FP32 complex multiply-accumulate on the
+ *                             vector ALUs (Sec. 4), 8 flops per complex MAC (Eq. 5).
+ *   XCORR_ACC_I8_MMA_I32      int8 matrix cores, int32 accumulation.  CI8 samples must lie
+ *                             in [-127, 127] (the conjugate side negates one operand).
+ *   XCORR_ACC_F16_MMA_F32     fp16 matrix cores, fp32 accumulation (exact: |sample| <= 2048).
+ *   XCORR_ACC_F8E4M3_MMA_F32  fp8 e4m3 matrix cores, fp32 accumulation; exact only for
+ *                             |sample| <= 16, so it accepts CI4, or CI8 after
+ *                             xcorr_set_max_abs(h, m) with m <= 16; otherwise the run is
+ *                             refused with XCORR_ERR_UNSUPPORTED.
+ *
+ * Exactness and the output type.  Integer samples with |component| <= max_abs grow any
+ * accumulator by at most 2*max_abs^2 per sample.  The library integrates in windows of at
+ * most floor((2^31-1) / (2*max_abs^2)) samples for int32 accumulators and
+ * floor(2^24 / (2*max_abs^2)) samples for fp32 accumulators (below 2^24 every fp32 partial
+ * sum of integers is exact, in any order); the wider accumulators of Sec. 2.3 then hold the
+ * total.  A run of one window writes ci32 (int32 accumulators) or c64 (fp32 accumulators);
+ * a run of several windows sums the windows on the GPU into ci64 or c128.  max_abs defaults
+ * to 127 for CI8 and 8 for CI4; xcorr_set_max_abs declares a smaller bound on the data
+ * (a promise by the caller, not checked).  CF32 input always runs one window and writes c64.
+ *
+ * Ownership and ordering.  Input and output are device pointers owned by the caller and
+ * must stay valid until the work enqueued on `stream` has completed.  Every run is
+ * asynchronous and stream ordered; the library never synchronises the host.  xcorr_run
+ * overwrites the output with the visibilities of its ntime samples.  A handle owns its
+ * device workspace and must not run on two streams at once.
+ *
+ * Errors.  Functions returning int give XCORR_OK (0) or a negative code below;
+ * constructors return NULL.  xcorr_last_error() describes the last failure of the calling
+ * thread.  Destroying NULL is a no-op.
+ */
+#ifndef XCORR_H
+#define XCORR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    XCORR_IN_CI8 = 0,
+    XCORR_IN_CI4 = 1,
+    XCORR_IN_CF32 = 2
+} xcorr_in_dtype;
+
+typedef enum {
+    XCORR_ACC_F32_CMAC = 0,
+    XCORR_ACC_I8_MMA_I32 = 1,
+    XCORR_ACC_F16_MMA_F32 = 2,
+    XCORR_ACC_F8E4M3_MMA_F32 = 3
+} xcorr_acc_dtype;
+
+typedef enum {
+    XCORR_OUT_CI32 = 0, /* int32 real, int32 imaginary */
+    XCORR_OUT_CI64 = 1, /* int64 real, int64 imaginary */
+    XCORR_OUT_C64 = 2,  /* float real, float imaginary */
+    XCORR_OUT_C128 = 3  /* double real, double imaginary */
+} xcorr_out_dtype;
+
+enum {
+    XCORR_OK = 0,
+    XCORR_ERR_INVALID_ARG = -1, /* bad size, pointer or enumerator */
+    XCORR_ERR_UNSUPPORTED = -2, /* combination that would not be exact */
+    XCORR_ERR_OOM = -3,         /* device or host allocation failed */
+    XCORR_ERR_HIP = -4,         /* a HIP runtime call failed (see xcorr_last_error) */
+    XCORR_ERR_RANGE = -5        /* a size exceeds what the library indexes */
+};
+
+/* ------------------------------------------------------------------ one correlation job */
+
+typedef struct xcorr_handle xcorr_handle_t;
+
+/*
+ * Plan a job of nstation stations x npol (1 or 2) polarisations, nchan channels and ntime
+ * samples (the sizes of Eq. 4 and Algorithm 1).  Uploads the job's work list to the
+ * current device.  Returns NULL on error.
+ */
+xcorr_handle_t *xcorr_create(int nstation, int npol, int nchan, int ntime,
+                             xcorr_in_dtype in_dtype, xcorr_acc_dtype acc_dtype);
+
+/* Declare that every real and imaginary component satisfies |v| <= max_abs (1..127 for
+ * CI8, 1..8 for CI4).  Re-plans the accumulation windows and may change the output type. */
+int xcorr_set_max_abs(xcorr_handle_t *h, int max_abs);
+
+/* Compute the visibilities of `in` (device, xcorr_in_bytes) into `out` (device,
+ * xcorr_out_bytes) on `stream` (0 = the null stream). */
+int xcorr_run(xcorr_handle_t *h, const void *in, void *out, hipStream_t stream);
+
+void xcorr_destroy(xcorr_handle_t *h);
+
+size_t xcorr_in_bytes(const xcorr_handle_t *h);
+size_t xcorr_out_bytes(const xcorr_handle_t *h);
+int xcorr_out_type(const xcorr_handle_t *h); /* an xcorr_out_dtype, or < 0 on error */
+
+/* Text of the last error on the calling thread ("" if none). */
+const char *xcorr_last_error(void);
+
+/* ------------------------------------------------------------------ host-only planning */
+
+/*
+ * What a plan does, without touching a GPU.  The useful work is the Eq. 5 count
+ * (one complex MAC per input pair of the lower triangle including autocorrelations, per
+ * channel and sample); the computed work adds the pairs that tiles on the diagonal and the
+ * zero padding of the last tile compute without storing (the wasted work of Sec. 6.1).
+ */
+typedef struct {
+    int nin;             /* nstation * npol */
+    int tile;            /* inputs per side of a square tile of the triangle */
+    int ntile_side;      /* ceil(nin / tile) */
+    int tiles_per_chan;  /* ntile_side * (ntile_side + 1) / 2 */
+    int window;          /* samples per accumulation window */
+    int nwindows;        /* ceil(ntime / window) */
+    int max_abs;         /* component bound the windows assume */
+    int out_dtype;       /* xcorr_out_dtype */
+    int64_t nitems;      /* work items (channel, tile, window) */
+    int64_t useful_cmacs;   /* nin*(nin+1)/2 * nchan * ntime */
+    int64_t computed_cmacs; /* complex MACs the kernels execute */
+    size_t in_bytes;
+    size_t out_bytes;
+} xcorr_plan_info;
+
+int xcorr_plan(int nstation, int npol, int nchan, int ntime, xcorr_in_dtype in_dtype,
+               xcorr_acc_dtype acc_dtype, int max_abs, xcorr_plan_info *info);
+
+/* Largest window (samples) for which the accumulators of acc_dtype stay exact with
+ * components bounded by max_abs; < 0 on a bad argument. */
+int64_t xcorr_window_limit(xcorr_in_dtype in_dtype, xcorr_acc_dtype acc_dtype, int max_abs);
+
+/* Inverse of the triangular tile numbering g = by*(by+1)/2 + bx, 0 <= bx <= by
+ * (Sec. 4.2), in exact integer arithmetic.  Returns XCORR_ERR_INVALID_ARG for g < 0. */
+int xcorr_tile_coords(int64_t g, int64_t *bx, int64_t *by);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* XCORR_H */

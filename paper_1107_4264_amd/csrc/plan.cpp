@@ -1,0 +1,169 @@
+// Host-side planner (no GPU calls).
+#include "plan.h"
+
+#include <limits.h>
+
+#include "xcorr.h"
+#include "xeng.h"
+
+namespace xc {
+
+size_t in_sample_bytes(int in_fmt)
+{
+    switch (in_fmt) {
+    case IN_CI8: return 2;
+    case IN_CI4: return 1;
+    case IN_CF32: return 8;
+    default: return 0;
+    }
+}
+
+size_t out_value_bytes(int out_dtype)
+{
+    switch (out_dtype) {
+    case OUT_CI32: return 8;
+    case OUT_CI64: return 16;
+    case OUT_C64: return 8;
+    case OUT_C128: return 16;
+    default: return 0;
+    }
+}
+
+int default_max_abs(int in_fmt, int acc)
+{
+    if (in_fmt == IN_CI4) return 8;
+    if (in_fmt == IN_CI8) return acc == ACC_I8 ? 127 : 128;
+    return 0;
+}
+
+static int max_abs_cap(int in_fmt, int acc)
+{
+    if (in_fmt == IN_CI4) return 8;
+    if (in_fmt == IN_CI8) return acc == ACC_I8 ? 127 : 128;
+    return 0;
+}
+
+// One sample adds at most |ar*br| + |ai*bi| <= 2*m^2 to a real or imaginary sum.
+int64_t window_limit(int in_fmt, int acc, int max_abs)
+{
+    if (in_fmt < IN_CI8 || in_fmt > IN_CF32 || acc < ACC_F32_CMAC || acc > ACC_F8) return -1;
+    if (in_fmt == IN_CF32) return acc == ACC_F32_CMAC ? INT64_MAX : -1;
+    if (max_abs < 1 || max_abs > max_abs_cap(in_fmt, acc)) return -1;
+    const int64_t per = 2 * (int64_t)max_abs * max_abs;
+    if (acc == ACC_I8) return ((int64_t)INT32_MAX) / per;
+    return ((int64_t)1 << 24) / per;  // every fp32 partial sum of integers <= 2^24 is exact
+}
+
+void tile_coords(int64_t g, int64_t *bx, int64_t *by)
+{
+    // b = floor((isqrt(8g + 1) - 1) / 2), with isqrt by Newton iteration on integers.
+    const uint64_t n = 8 * (uint64_t)g + 1;
+    uint64_t x = n, y = (x + 1) / 2;
+    while (y < x) {
+        x = y;
+        y = (x + n / x) / 2;
+    }
+    int64_t b = (int64_t)((x - 1) / 2);
+    while (b * (b + 1) / 2 > g) --b;
+    while ((b + 1) * (b + 2) / 2 <= g) ++b;
+    *by = b;
+    *bx = g - b * (b + 1) / 2;
+}
+
+int64_t computed_pairs_per_sample(int nin, int tile, int acc)
+{
+    const int64_t nts = (nin + tile - 1) / tile;
+    if (acc == ACC_F32_CMAC) return nts * (nts + 1) / 2 * (int64_t)tile * tile;
+    // MFMA kernels: 32x32 blocks, skipping blocks strictly above the diagonal of a diagonal
+    // tile and blocks that start beyond the last input.
+    const int nbs = tile / 32;
+    int64_t total = 0;
+    for (int64_t by = 0; by < nts; ++by)
+        for (int64_t bx = 0; bx <= by; ++bx)
+            for (int r = 0; r < nbs; ++r)
+                for (int c = 0; c < nbs; ++c) {
+                    if (bx == by && r < c) continue;
+                    if (by * tile + r * 32 >= nin || bx * tile + c * 32 >= nin) continue;
+                    total += 32 * 32;
+                }
+    return total;
+}
+
+int make_plan(int nstation, int npol, int nchan, int ntime, int in_fmt, int acc, int max_abs,
+              int tile_override, Plan *pl, std::string *err)
+{
+    if (!pl) {
+        *err = "null plan";
+        return XCORR_ERR_INVALID_ARG;
+    }
+    if (nstation < 1 || (npol != 1 && npol != 2) || nchan < 1 || ntime < 0) {
+        *err = "need nstation >= 1, npol in {1, 2}, nchan >= 1, ntime >= 0";
+        return XCORR_ERR_INVALID_ARG;
+    }
+    if (in_fmt < IN_CI8 || in_fmt > IN_CF32 || acc < ACC_F32_CMAC || acc > ACC_F8) {
+        *err = "unknown input format or arithmetic path";
+        return XCORR_ERR_INVALID_ARG;
+    }
+    if (in_fmt == IN_CF32 && acc != ACC_F32_CMAC) {
+        *err = "float input is only accepted by the FP32 CMAC path";
+        return XCORR_ERR_UNSUPPORTED;
+    }
+    const int64_t nin64 = (int64_t)nstation * npol;
+    if (nin64 > 65536) {
+        *err = "at most 65536 inputs (stations x polarisations)";
+        return XCORR_ERR_RANGE;
+    }
+    if (max_abs == 0) max_abs = default_max_abs(in_fmt, acc);
+    if (in_fmt != IN_CF32 && (max_abs < 1 || max_abs > max_abs_cap(in_fmt, acc))) {
+        *err = "max_abs out of range for the sample format";
+        return XCORR_ERR_INVALID_ARG;
+    }
+    if (acc == ACC_F8 && max_abs > 16) {
+        *err = "fp8 e4m3 is exact only for |sample| <= 16: use CI4 or declare max_abs <= 16";
+        return XCORR_ERR_UNSUPPORTED;
+    }
+    Plan p;
+    p.nstation = nstation;
+    p.npol = npol;
+    p.nchan = nchan;
+    p.ntime = ntime;
+    p.in_fmt = in_fmt;
+    p.acc = acc;
+    p.max_abs = in_fmt == IN_CF32 ? 0 : max_abs;
+    p.nin = (int)nin64;
+    int tile = acc == ACC_F32_CMAC ? 64 : (p.nin > 64 ? 128 : 64);
+    if (tile_override) {
+        if (acc == ACC_F32_CMAC ? tile_override != 64 : (tile_override != 64 && tile_override != 128)) {
+            *err = "unsupported tile size";
+            return XCORR_ERR_INVALID_ARG;
+        }
+        tile = tile_override;
+    }
+    p.tile = tile;
+    p.ntile_side = (p.nin + tile - 1) / tile;
+    p.tiles_per_chan = p.ntile_side * (p.ntile_side + 1) / 2;
+
+    const int64_t lim = window_limit(in_fmt, acc, in_fmt == IN_CF32 ? 1 : max_abs);
+    if (ntime <= lim) {
+        p.window = ntime > 0 ? ntime : 1;
+        p.nwindows = ntime > 0 ? 1 : 0;
+    } else {
+        const int64_t w = lim >= 64 ? (lim / 64) * 64 : lim;
+        p.window = (int)w;
+        p.nwindows = (int)((ntime + w - 1) / w);
+    }
+    const bool wide = p.nwindows > 1;
+    if (acc == ACC_I8) p.out_dtype = wide ? OUT_CI64 : OUT_CI32;
+    else p.out_dtype = wide ? OUT_C128 : OUT_C64;
+
+    const int64_t nbl = (int64_t)nstation * (nstation + 1) / 2;
+    p.nitems = (int64_t)nchan * p.tiles_per_chan * p.nwindows;
+    p.useful_cmacs = nin64 * (nin64 + 1) / 2 * nchan * (int64_t)ntime;
+    p.computed_cmacs = computed_pairs_per_sample(p.nin, tile, acc) * nchan * (int64_t)ntime;
+    p.in_bytes = (size_t)ntime * nchan * (size_t)p.nin * in_sample_bytes(in_fmt);
+    p.out_bytes = (size_t)nchan * nbl * npol * npol * out_value_bytes(p.out_dtype);
+    *pl = p;
+    return XCORR_OK;
+}
+
+}  // namespace xc

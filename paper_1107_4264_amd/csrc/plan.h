@@ -1,0 +1,41 @@
+// Host-side planner: tile geometry, accumulation windows, output type and work accounting.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <string>
+
+namespace xc {
+
+struct Plan {
+    int nstation = 0, npol = 0, nchan = 0, ntime = 0;
+    int in_fmt = 0, acc = 0, max_abs = 0;
+    int nin = 0, tile = 0, ntile_side = 0, tiles_per_chan = 0;
+    int window = 0, nwindows = 0, out_dtype = 0;
+    int64_t nitems = 0, useful_cmacs = 0, computed_cmacs = 0;
+    size_t in_bytes = 0, out_bytes = 0;
+};
+
+// Largest exact window in samples (INT64_MAX when unbounded), or -1 on a bad argument.
+int64_t window_limit(int in_fmt, int acc, int max_abs);
+
+// Default component bound of a sample format for an arithmetic path.
+int default_max_abs(int in_fmt, int acc);
+
+// Fill `pl`.  tile_override 0 picks the default tile.  Returns an XCORR_* code and sets
+// *err on failure.
+int make_plan(int nstation, int npol, int nchan, int ntime, int in_fmt, int acc, int max_abs,
+              int tile_override, Plan *pl, std::string *err);
+
+// Exact inverse of g = by*(by+1)/2 + bx, 0 <= bx <= by.
+void tile_coords(int64_t g, int64_t *bx, int64_t *by);
+
+// Complex MACs the kernels execute per channel and sample for a tile geometry.
+int64_t computed_pairs_per_sample(int nin, int tile, int acc);
+
+// Bytes per sample of an input format; bytes per complex value of an output type.
+size_t in_sample_bytes(int in_fmt);
+size_t out_value_bytes(int out_dtype);
+
+}  // namespace xc

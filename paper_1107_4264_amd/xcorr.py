@@ -1,0 +1,219 @@
+"""Thin ctypes binding of ``libxcorr.so`` (the C ABI declared in ``include/xcorr.h``).
+
+Functions carry the C names; they only marshal arguments.  Every step of the X-engine
+runs in the HIP kernels of the library.  The convenience class :class:`Correlator` takes
+torch tensors for device memory and uses torch's current HIP stream.
+
+There is no fallback: if the library is missing or fails to load, importing this module
+raises.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.environ.get("XCORR_LIB", os.path.join(HERE, "libxcorr.so"))
+HEADER = os.path.join(os.path.dirname(HERE), "include", "xcorr.h")
+
+# enumerators of xcorr.h
+IN_CI8, IN_CI4, IN_CF32 = 0, 1, 2
+ACC_F32_CMAC, ACC_I8_MMA_I32, ACC_F16_MMA_F32, ACC_F8E4M3_MMA_F32 = 0, 1, 2, 3
+OUT_CI32, OUT_CI64, OUT_C64, OUT_C128 = 0, 1, 2, 3
+OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_OOM, ERR_HIP, ERR_RANGE = 0, -1, -2, -3, -4, -5
+
+IN_NAMES = {"ci8": IN_CI8, "ci4": IN_CI4, "cf32": IN_CF32}
+ACC_NAMES = {"f32": ACC_F32_CMAC, "i8": ACC_I8_MMA_I32, "f16": ACC_F16_MMA_F32, "f8": ACC_F8E4M3_MMA_F32}
+
+
+class XcorrError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"xcorr error {code}: {msg}")
+        self.code = code
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [
+        ("nin", ctypes.c_int), ("tile", ctypes.c_int), ("ntile_side", ctypes.c_int),
+        ("tiles_per_chan", ctypes.c_int), ("window", ctypes.c_int), ("nwindows", ctypes.c_int),
+        ("max_abs", ctypes.c_int), ("out_dtype", ctypes.c_int), ("nitems", ctypes.c_int64),
+        ("useful_cmacs", ctypes.c_int64), ("computed_cmacs", ctypes.c_int64),
+        ("in_bytes", ctypes.c_size_t), ("out_bytes", ctypes.c_size_t),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built: run python -m paper_1107_4264_amd.build")
+    # torch ships its own HIP runtime with the same soname.  Loading torch first makes the
+    # library bind to that one runtime; the other order would put two runtimes in the
+    # process, and the second one finds no device.
+    import torch  # noqa: F401
+
+    lib = ctypes.CDLL(LIB_PATH)
+    c_int, c_i64, c_sz, c_vp = ctypes.c_int, ctypes.c_int64, ctypes.c_size_t, ctypes.c_void_p
+    sig = {
+        "xcorr_create": (c_vp, [c_int, c_int, c_int, c_int, c_int, c_int]),
+        "xcorr_set_max_abs": (c_int, [c_vp, c_int]),
+        "xcorr_run": (c_int, [c_vp, c_vp, c_vp, c_vp]),
+        "xcorr_destroy": (None, [c_vp]),
+        "xcorr_in_bytes": (c_sz, [c_vp]),
+        "xcorr_out_bytes": (c_sz, [c_vp]),
+        "xcorr_out_type": (c_int, [c_vp]),
+        "xcorr_last_error": (ctypes.c_char_p, []),
+        "xcorr_plan": (c_int, [c_int, c_int, c_int, c_int, c_int, c_int, c_int, ctypes.POINTER(PlanInfo)]),
+        "xcorr_window_limit": (c_i64, [c_int, c_int, c_int]),
+        "xcorr_tile_coords": (c_int, [c_i64, ctypes.POINTER(c_i64), ctypes.POINTER(c_i64)]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = _load()
+
+
+def lib():
+    return _lib
+
+
+def header_functions(path: str = HEADER):
+    """Names of the functions declared in the public header."""
+    text = open(path).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(xcorr_[a-z0-9_]+)\s*\(", text)))
+
+
+def last_error() -> str:
+    return (_lib.xcorr_last_error() or b"").decode()
+
+
+def _check(rc):
+    if rc < 0:
+        raise XcorrError(rc, last_error())
+    return rc
+
+
+# ------------------------------------------------------------------ C-named wrappers
+
+def xcorr_create(nstation, npol, nchan, ntime, in_dtype, acc_dtype):
+    h = _lib.xcorr_create(nstation, npol, nchan, ntime, in_dtype, acc_dtype)
+    if not h:
+        raise XcorrError(-1, last_error())
+    return h
+
+
+def xcorr_set_max_abs(h, max_abs):
+    return _check(_lib.xcorr_set_max_abs(h, max_abs))
+
+
+def xcorr_run(h, in_ptr, out_ptr, stream_ptr):
+    return _check(_lib.xcorr_run(h, in_ptr, out_ptr, stream_ptr))
+
+
+def xcorr_destroy(h):
+    _lib.xcorr_destroy(h)
+
+
+def xcorr_in_bytes(h):
+    return int(_lib.xcorr_in_bytes(h))
+
+
+def xcorr_out_bytes(h):
+    return int(_lib.xcorr_out_bytes(h))
+
+
+def xcorr_out_type(h):
+    return _check(_lib.xcorr_out_type(h))
+
+
+def xcorr_plan(nstation, npol, nchan, ntime, in_dtype, acc_dtype, max_abs=0):
+    info = PlanInfo()
+    _check(_lib.xcorr_plan(nstation, npol, nchan, ntime, in_dtype, acc_dtype, max_abs, ctypes.byref(info)))
+    return info.as_dict()
+
+
+def xcorr_window_limit(in_dtype, acc_dtype, max_abs):
+    return _check(_lib.xcorr_window_limit(in_dtype, acc_dtype, max_abs))
+
+
+def xcorr_tile_coords(g):
+    bx, by = ctypes.c_int64(), ctypes.c_int64()
+    _check(_lib.xcorr_tile_coords(g, ctypes.byref(bx), ctypes.byref(by)))
+    return bx.value, by.value
+
+
+# ------------------------------------------------------------------ torch convenience
+
+def out_torch_dtype(out_type):
+    import torch
+
+    return {OUT_CI32: torch.int32, OUT_CI64: torch.int64, OUT_C64: torch.float32,
+            OUT_C128: torch.float64}[out_type]
+
+
+def _stream_ptr(stream):
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Correlator:
+    """One planned job.  ``in_dtype`` / ``acc`` take the enumerators or the short names
+    ('ci8', 'ci4', 'cf32' / 'f32', 'i8', 'f16', 'f8')."""
+
+    def __init__(self, nstation, npol, nchan, ntime, in_dtype="ci8", acc="f16", max_abs=None):
+        self.nstation, self.npol, self.nchan, self.ntime = nstation, npol, nchan, ntime
+        self.in_dtype = IN_NAMES.get(in_dtype, in_dtype)
+        self.acc = ACC_NAMES.get(acc, acc)
+        self.h = xcorr_create(nstation, npol, nchan, ntime, self.in_dtype, self.acc)
+        if max_abs is not None:
+            xcorr_set_max_abs(self.h, int(max_abs))
+
+    def close(self):
+        if self.h:
+            xcorr_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def out_type(self):
+        return xcorr_out_type(self.h)
+
+    @property
+    def nbl(self):
+        return self.nstation * (self.nstation + 1) // 2
+
+    def out_shape(self):
+        return (self.nchan, self.nbl, self.npol * self.npol, 2)
+
+    def empty_out(self, device="cuda"):
+        import torch
+
+        return torch.empty(self.out_shape(), dtype=out_torch_dtype(self.out_type), device=device)
+
+    def run(self, x, out=None, stream=None):
+        """x: device tensor holding xcorr_in_bytes bytes of samples; returns the output."""
+        if not x.is_cuda:
+            raise ValueError("input must be a device tensor")
+        if x.numel() * x.element_size() != xcorr_in_bytes(self.h):
+            raise ValueError("input size does not match the plan")
+        if out is None:
+            out = self.empty_out(x.device)
+        if out.numel() * out.element_size() != xcorr_out_bytes(self.h) or out.dtype != out_torch_dtype(self.out_type):
+            raise ValueError("output buffer does not match the plan")
+        xcorr_run(self.h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream))
+        return out

@@ -1,0 +1,169 @@
+"""Host-side checks of the C ABI (no GPU): the library loads and exports every function the
+header declares; the planner's tile numbering, accumulation windows, output types, work
+accounting and argument checks."""
+
+from __future__ import annotations
+
+import ctypes
+import json
+import os
+import subprocess
+
+import pytest
+
+from paper_1107_4264_amd import xcorr as X
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def test_exports_every_header_function():
+    names = X.header_functions()
+    assert "xcorr_create" in names and "xcorr_run" in names
+    out = subprocess.run(["nm", "-D", "--defined-only", X.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if line.strip()}
+    missing = [n for n in names if n not in exported]
+    assert not missing, f"not exported: {missing}"
+    for n in names:
+        assert hasattr(X.lib(), n)
+
+
+def test_tile_coords_exhaustive():
+    """Triangular numbering g = by(by+1)/2 + bx with bx <= by (Sec. 4.2), inverted exactly,
+    checked against enumeration for every g < 2^21 and at large g."""
+    g = 0
+    for by in range(2048):
+        for bx in range(by + 1):
+            if g % 97 == 0 or by < 64:
+                assert X.xcorr_tile_coords(g) == (bx, by)
+            g += 1
+    for by in [10**6, 2**31 - 1, 3 * 10**9]:
+        base = by * (by + 1) // 2
+        assert X.xcorr_tile_coords(base) == (0, by)
+        assert X.xcorr_tile_coords(base + by) == (by, by)
+        assert X.xcorr_tile_coords(base - 1) == (by - 1, by - 1)
+    with pytest.raises(X.XcorrError):
+        X.xcorr_tile_coords(-1)
+
+
+def test_window_limits():
+    # int32 accumulators, 8-bit samples within [-127, 127]: floor((2^31-1) / (2*127^2))
+    assert X.xcorr_window_limit(X.IN_CI8, X.ACC_I8_MMA_I32, 127) == 66572
+    # fp32 accumulators: floor(2^24 / (2 m^2))
+    assert X.xcorr_window_limit(X.IN_CI8, X.ACC_F16_MMA_F32, 128) == 512
+    assert X.xcorr_window_limit(X.IN_CI8, X.ACC_F32_CMAC, 127) == 520
+    assert X.xcorr_window_limit(X.IN_CI4, X.ACC_F8E4M3_MMA_F32, 8) == 131072
+    assert X.xcorr_window_limit(X.IN_CI4, X.ACC_I8_MMA_I32, 8) == 16777215
+    assert X.xcorr_window_limit(X.IN_CI8, X.ACC_F16_MMA_F32, 18) == 25890
+    with pytest.raises(X.XcorrError):
+        X.xcorr_window_limit(X.IN_CI8, X.ACC_I8_MMA_I32, 128)  # -128 cannot be negated in int8
+    with pytest.raises(X.XcorrError):
+        X.xcorr_window_limit(X.IN_CI4, X.ACC_I8_MMA_I32, 9)
+
+
+def test_window_bound_is_tight_for_ci4():
+    """4-bit worst case per sample is 2*8^2 = 128 (an autocorrelation of -8 - 8i)."""
+    assert (-8) * (-8) + (-8) * (-8) == 128
+    assert X.xcorr_window_limit(X.IN_CI4, X.ACC_F16_MMA_F32, 8) * 128 == 2**24
+
+
+@pytest.mark.parametrize("acc", [X.ACC_F32_CMAC, X.ACC_I8_MMA_I32, X.ACC_F16_MMA_F32])
+def test_plan_windows_and_types(acc):
+    p = X.xcorr_plan(128, 2, 1024, 1000, X.IN_CI8, acc, 18)
+    assert p["nwindows"] == 1
+    assert p["out_dtype"] == (X.OUT_CI32 if acc == X.ACC_I8_MMA_I32 else X.OUT_C64)
+    p = X.xcorr_plan(128, 2, 4, 70000, X.IN_CI8, acc, 0)
+    if acc == X.ACC_I8_MMA_I32:
+        assert p["nwindows"] == 2 and p["out_dtype"] == X.OUT_CI64
+        assert p["window"] % 64 == 0 and p["window"] <= 66572
+    else:
+        assert p["nwindows"] > 1 and p["out_dtype"] == X.OUT_C128
+        assert p["window"] * 2 * p["max_abs"] ** 2 <= 2**24
+
+
+def test_plan_sizes_config_shapes():
+    # 32 stations x 2 pol, 16 channels, 256 samples: 2080 input pairs (Eq. 5), 528 baselines
+    p = X.xcorr_plan(32, 2, 16, 256, X.IN_CI8, X.ACC_F32_CMAC, 8)
+    assert p["nin"] == 64
+    assert p["useful_cmacs"] == 2080 * 16 * 256
+    assert p["in_bytes"] == 256 * 16 * 64 * 2
+    assert p["out_bytes"] == 16 * 528 * 4 * 8
+    # 128 stations x 2 pol at 1024 channels: three 128-tiles per channel on the MFMA paths
+    p = X.xcorr_plan(128, 2, 1024, 1000, X.IN_CI8, X.ACC_F16_MMA_F32, 18)
+    assert (p["tile"], p["ntile_side"], p["tiles_per_chan"]) == (128, 2, 3)
+    # 32x32 blocks on or below the diagonal: 16 + 10 + 10 blocks of 1024 pairs
+    assert p["computed_cmacs"] == 36 * 1024 * 1024 * 1000
+    # 512 stations x 2 pol, 4-bit: 36 tiles per channel
+    p = X.xcorr_plan(512, 2, 256, 4096, X.IN_CI4, X.ACC_I8_MMA_I32, 0)
+    assert p["tiles_per_chan"] == 36 and p["nwindows"] == 1 and p["out_dtype"] == X.OUT_CI32
+    assert p["in_bytes"] == 4096 * 256 * 1024
+
+
+def test_waste_factor_matches_paper():
+    """With whole diagonal tiles computed (the paper's kernel), computed / useful work is
+    2(N + RT) / (2N + 1) for N dual-pol stations and tiles of RT stations (Sec. 6.1)."""
+    with open(os.path.join(GOLDEN, "paper_numbers.json")) as fh:
+        gold = json.load(fh)["waste_factor"]
+    for N in gold["stations"]:
+        p = X.xcorr_plan(N, 2, 1, 1, X.IN_CI8, X.ACC_F32_CMAC, 0)
+        RT = p["tile"] // 2
+        ratio = p["computed_cmacs"] / p["useful_cmacs"]
+        assert ratio == pytest.approx(2 * (N + RT) / (2 * N + 1), rel=1e-12)
+
+
+def test_diagonal_skip_reduces_waste():
+    p = X.xcorr_plan(128, 2, 1, 1, X.IN_CI8, X.ACC_F16_MMA_F32, 0)
+    assert p["useful_cmacs"] / p["computed_cmacs"] == pytest.approx(32896 / 36864)
+
+
+@pytest.mark.parametrize("args,code", [
+    ((0, 2, 1, 1, X.IN_CI8, X.ACC_F16_MMA_F32, 0), X.ERR_INVALID_ARG),
+    ((4, 3, 1, 1, X.IN_CI8, X.ACC_F16_MMA_F32, 0), X.ERR_INVALID_ARG),
+    ((4, 2, 0, 1, X.IN_CI8, X.ACC_F16_MMA_F32, 0), X.ERR_INVALID_ARG),
+    ((4, 2, 1, -1, X.IN_CI8, X.ACC_F16_MMA_F32, 0), X.ERR_INVALID_ARG),
+    ((4, 2, 1, 1, 7, X.ACC_F16_MMA_F32, 0), X.ERR_INVALID_ARG),
+    ((4, 2, 1, 1, X.IN_CF32, X.ACC_I8_MMA_I32, 0), X.ERR_UNSUPPORTED),
+    ((4, 2, 1, 1, X.IN_CI8, X.ACC_F8E4M3_MMA_F32, 127), X.ERR_UNSUPPORTED),
+    ((4, 2, 1, 1, X.IN_CI8, X.ACC_I8_MMA_I32, 128), X.ERR_INVALID_ARG),
+    ((40000, 2, 1, 1, X.IN_CI8, X.ACC_I8_MMA_I32, 0), X.ERR_RANGE),
+])
+def test_plan_rejects(args, code):
+    with pytest.raises(X.XcorrError) as ei:
+        X.xcorr_plan(*args)
+    assert ei.value.code == code
+    assert X.last_error()
+
+
+def test_fp8_accepts_small_bound_and_ci4():
+    assert X.xcorr_plan(4, 2, 1, 1, X.IN_CI8, X.ACC_F8E4M3_MMA_F32, 16)["out_dtype"] == X.OUT_C64
+    assert X.xcorr_plan(4, 2, 1, 1, X.IN_CI4, X.ACC_F8E4M3_MMA_F32, 0)["max_abs"] == 8
+
+
+def test_empty_integration_plans_no_items():
+    p = X.xcorr_plan(4, 2, 3, 0, X.IN_CI8, X.ACC_I8_MMA_I32, 0)
+    assert p["nitems"] == 0 and p["out_dtype"] == X.OUT_CI32 and p["in_bytes"] == 0
+
+
+def test_destroy_null_is_noop():
+    X.xcorr_destroy(ctypes.c_void_p(0))
+    assert X.xcorr_in_bytes(ctypes.c_void_p(0)) == 0
+
+
+def test_table1_model():
+    """The intensity model reproduces the paper's Table 1 from its hardware numbers."""
+    from paper_1107_4264_amd import perfmodel as pm
+
+    with open(os.path.join(GOLDEN, "paper_numbers.json")) as fh:
+        gold = json.load(fh)
+    hw, lv = gold["gtx480"], gold["table1"]["levels"]
+    assert round(hw["peak_gflops"] / hw["device_gbps"], 1) == lv[2]["ai"]
+    assert round(hw["peak_gflops"] / hw["pcie_gbps"]) == lv[3]["ai"]
+    assert pm.required_square_tile(lv[1]["ai"]) == lv[0]["tile"]
+    assert pm.required_square_tile(lv[2]["ai"]) == lv[1]["tile"]
+    assert pm.required_square_tile(lv[3]["ai"]) == lv[2]["tile"]
+    assert pm.tile_registers(1, 1) == 16
+    assert pm.staging_bytes(8, 8) == lv[1]["resources_bytes"]
+    assert pm.staging_bytes(210, 210) == lv[2]["resources_bytes"]
+    assert pm.tile_ai(1, 1, 1, word=4.0) == pytest.approx(32 / 96)
+    assert pm.tile_ai(1, 1, 1) == pytest.approx(gold["intensity"]["single_baseline_ai"])
+    assert pm.tile_ai(8, 8, 1e9) == pytest.approx(8.0, rel=1e-6)
