@@ -77,6 +77,11 @@ int enqueue_job(const Plan &pl, const void *in, void *out, hipStream_t stream)
 {
     if (pl.acc == ACC_F8 && pl.max_abs > 16)
         return fail(XCORR_ERR_UNSUPPORTED, "fp8 e4m3 needs max_abs <= 16 (call xcorr_set_max_abs)");
+    // The matrix-core kernels address one block of 64 samples of a channel with 32-bit
+    // buffer offsets.
+    if (pl.acc != ACC_F32_CMAC &&
+        64.0 * (double)pl.nchan * pl.nin * (double)in_sample_bytes(pl.in_fmt) >= 4294901760.0)
+        return fail(XCORR_ERR_RANGE, "nchan * nin too large: 64 samples of all channels must span < 4 GiB");
     XJob j = job_from_plan(pl, in, out);
     int e;
     if (pl.nwindows != 1) {

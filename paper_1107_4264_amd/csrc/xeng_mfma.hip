@@ -25,6 +25,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "xeng.h"
 
 namespace xc {
@@ -149,8 +151,24 @@ __device__ __forceinline__ uint32_t f16_bits(int v)
 {
     return (uint32_t)__builtin_bit_cast(unsigned short, (_Float16)(short)v);
 }
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef int i32x4v __attribute__((ext_vector_type(4)));
 
-// ---------------------------------------------------------------- the tile kernel body
+// Two (re, im) int8 pairs packed in one word -> two words of (fp16 re, fp16 im).  For v in
+// [-128, 127] the fp16 number with bits 0x6400 | (v ^ 0x80) is exactly 1152 + v, so a byte
+// permute and one packed fp16 subtraction convert both parts exactly.
+__device__ __forceinline__ void ci8x2_to_f16(uint32_t w, uint32_t &lo, uint32_t &hi)
+{
+    const uint32_t x = w ^ 0x80808080u;
+    const uint32_t a = __builtin_amdgcn_perm(0x64646464u, x, 0x04010400u);
+    const uint32_t b = __builtin_amdgcn_perm(0x64646464u, x, 0x04030402u);
+    const f16x2 bias = {(_Float16)(-1152.0f), (_Float16)(-1152.0f)};
+    lo = __builtin_bit_cast(uint32_t, __builtin_bit_cast(f16x2, a) + bias);
+    hi = __builtin_bit_cast(uint32_t, __builtin_bit_cast(f16x2, b) + bias);
+}
+
+// ---------------------------------------------------------------- tile geometry
 
 template <int ACC, int IN, int TILE>
 struct Tile {
@@ -167,90 +185,14 @@ struct Tile {
     static constexpr int LW = CI * BPC / 4;                  // words per row load
     static constexpr int NT = NTG * (TILE / CI);             // staging tasks per side
     static constexpr int NB = TILE / 64;                     // 32x32 blocks per wave side
-    static constexpr int WT = TILE / 2;                      // wave sub-tile side
     static constexpr int SIDE_BYTES = NTG * PLANES * TILE * 16;
     static constexpr int LDS_BYTES = 2 * 2 * SIDE_BYTES;     // 2 buffers x 2 sides
-    static_assert(NT <= 128 || TILE > 128, "one staging task per thread and side");
+    static constexpr int FULL = (1 << (NB * NB)) - 1;        // every block of the wave
+    static constexpr int DIAG = NB == 2 ? 0xD : 1;           // blocks (0,0), (1,0), (1,1)
+    static constexpr int DEPTH = ACC == ACC_F16 ? 2 : 1;     // register prefetch depth
+    static_assert(2 * NT <= 256, "at most one staging task per thread");
     static_assert(TB % (2 * G) == 0, "time block holds whole K-steps");
 };
-
-template <int ACC, int IN, int TILE>
-__device__ __forceinline__ void load_task(const XJob &p, int f, int side_row0, int t0, int t_end,
-                                          int tg, int chunk,
-                                          uint32_t (&rows)[Tile<ACC, IN, TILE>::G][Tile<ACC, IN, TILE>::LW])
-{
-    using T = Tile<ACC, IN, TILE>;
-    const uint8_t *in = (const uint8_t *)p.in;
-    const int i0 = side_row0 + chunk * T::CI;
-#pragma unroll
-    for (int u = 0; u < T::G; ++u) {
-        const int t = t0 + tg * T::G + u;
-#pragma unroll
-        for (int k = 0; k < T::LW; ++k) rows[u][k] = 0u;
-        if (t >= t_end || i0 >= p.nin) continue;
-        const uint8_t *src = in + (((int64_t)t * p.nchan + f) * p.nin + i0) * T::BPC;
-        if (p.load_mode == LOAD_VEC) {
-            if constexpr (T::LW == 4) {
-                const uint4 v = *(const uint4 *)src;
-                rows[u][0] = v.x; rows[u][1] = v.y; rows[u][2] = v.z; rows[u][3] = v.w;
-            } else {
-                const uint2 v = *(const uint2 *)src;
-                rows[u][0] = v.x; rows[u][1] = v.y;
-            }
-        } else if (p.load_mode == LOAD_WORD) {
-            constexpr int PER_WORD = 4 / T::BPC;
-#pragma unroll
-            for (int k = 0; k < T::LW; ++k)
-                if (i0 + k * PER_WORD < p.nin) rows[u][k] = *(const uint32_t *)(src + 4 * k);
-        } else {
-#pragma unroll
-            for (int b = 0; b < T::LW * 4; ++b)
-                if (i0 + b / T::BPC < p.nin) rows[u][b >> 2] |= (uint32_t)src[b] << (8 * (b & 3));
-        }
-    }
-}
-
-// Pack input e of a task's loaded rows into its LDS unit (WORDS words).
-template <int ACC, int IN, int TILE>
-__device__ __forceinline__ void pack_unit(
-    const uint32_t (&rows)[Tile<ACC, IN, TILE>::G][Tile<ACC, IN, TILE>::LW], int e,
-    uint32_t (&u)[Tile<ACC, IN, TILE>::WORDS])
-{
-    using T = Tile<ACC, IN, TILE>;
-    if constexpr (ACC == ACC_I8) {
-        if constexpr (IN == IN_CI8) {
-            const uint32_t sel = (e & 1) ? 0x07060302u : 0x05040100u;
-#pragma unroll
-            for (int m = 0; m < 4; ++m)
-                u[m] = __builtin_amdgcn_perm(rows[2 * m + 1][e >> 1], rows[2 * m][e >> 1], sel);
-        } else {
-#pragma unroll
-            for (int m = 0; m < 4; ++m) {
-                int r0, i0, r1, i1;
-                pair_of<IN>(rows[2 * m], e, r0, i0);
-                pair_of<IN>(rows[2 * m + 1], e, r1, i1);
-                u[m] = (uint32_t)(r0 & 0xFF) | ((uint32_t)(i0 & 0xFF) << 8) |
-                       ((uint32_t)(r1 & 0xFF) << 16) | ((uint32_t)(i1 & 0xFF) << 24);
-            }
-        }
-    } else if constexpr (ACC == ACC_F16) {
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            int re, im;
-            pair_of<IN>(rows[m], e, re, im);
-            u[m] = f16_bits(re) | (f16_bits(im) << 16);
-        }
-    } else {
-#pragma unroll
-        for (int m = 0; m < 8; ++m) {
-            int r0, i0, r1, i1;
-            pair_of<IN>(rows[2 * m], e, r0, i0);
-            pair_of<IN>(rows[2 * m + 1], e, r1, i1);
-            uint32_t w = __builtin_amdgcn_cvt_pk_fp8_f32((float)r0, (float)i0, 0, false);
-            u[m] = __builtin_amdgcn_cvt_pk_fp8_f32((float)r1, (float)i1, w, true);
-        }
-    }
-}
 
 template <int ACC, int IN, int TILE>
 __device__ __forceinline__ uint32_t lds_off(int side, int tg, int plane, int row)
@@ -260,12 +202,310 @@ __device__ __forceinline__ uint32_t lds_off(int side, int tg, int plane, int row
                       ((tg * T::PLANES + plane) * TILE + (row ^ (tg & T::SWZ))) * 16);
 }
 
+// ---------------------------------------------------------------- staging
+
+// Buffer descriptors over the rows of the time blocks of one channel: block k covers rows
+// t_begin + k*TB .. min(t_begin + (k+1)*TB, t_end) - 1, each a run of nin samples.  Loads
+// beyond a descriptor's size return zero in hardware, which pads the last block of a
+// window and the tile beyond the last input without branches; blocks past the window get
+// an empty descriptor.  All fields are wave-uniform and kept in scalar registers.
+struct BlockRsrc {
+    uint64_t base0;      // address of row t_begin of channel f
+    uint64_t blk_bytes;  // TB rows
+    uint32_t full_rec;   // bytes of a whole block
+    uint32_t last_rec;   // bytes of the last block
+    int nblk;
+
+    __device__ __forceinline__ BlockRsrc(const XJob &p, int f, int t_begin, int t_end, int tb, int bpc)
+    {
+        const uint64_t row_stride = (uint64_t)p.nchan * p.nin * bpc;
+        const uint64_t b0 = (uint64_t)p.in + (((uint64_t)t_begin * p.nchan + f) * p.nin) * bpc;
+        // readfirstlane returns int: widen through uint32_t, or a low word >= 2^31 would
+        // sign-extend into the high word of the address
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)b0);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(b0 >> 32));
+        base0 = ((uint64_t)hi << 32) | (uint64_t)lo;
+        blk_bytes = (uint64_t)tb * row_stride;
+        nblk = __builtin_amdgcn_readfirstlane((t_end - t_begin + tb - 1) / tb);
+        full_rec = __builtin_amdgcn_readfirstlane((uint32_t)(tb * row_stride));
+        last_rec = __builtin_amdgcn_readfirstlane((uint32_t)((t_end - t_begin - (nblk - 1) * tb) * row_stride));
+    }
+
+    __device__ __forceinline__ __amdgpu_buffer_rsrc_t get(int blk) const
+    {
+        const uint32_t rec = blk < nblk - 1 ? full_rec : (blk == nblk - 1 ? last_rec : 0u);
+        return __builtin_amdgcn_make_buffer_rsrc((void *)(base0 + (uint64_t)blk * blk_bytes), (short)0, (int)rec,
+                                                 0x00020000);
+    }
+};
+
+constexpr uint32_t OOB = 0xFFFFFFF0u;  // offset beyond any descriptor: the load returns zero
+
+// Loads of one staging task: G rows (block rows row0 .. row0+G-1) of CI inputs from i0.
+// MODE is the job's LoadMode: whole chunks (rows aligned to the chunk), 32-bit words (rows
+// word aligned) or single bytes.
+template <int ACC, int IN, int TILE, int MODE>
+__device__ __forceinline__ void load_rows(__amdgpu_buffer_rsrc_t rs, uint32_t row_stride, int row0, int i0,
+                                          int nin, uint32_t (&rows)[Tile<ACC, IN, TILE>::G][Tile<ACC, IN, TILE>::LW])
+{
+    using T = Tile<ACC, IN, TILE>;
+#pragma unroll
+    for (int u = 0; u < T::G; ++u) {
+        const uint32_t roff = (uint32_t)(row0 + u) * row_stride;
+        if constexpr (MODE == LOAD_VEC) {
+            const uint32_t off = i0 < nin ? roff + (uint32_t)i0 * T::BPC : OOB;
+            if constexpr (T::LW == 4) {
+                const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, 0);
+                rows[u][0] = v[0]; rows[u][1] = v[1]; rows[u][2] = v[2]; rows[u][3] = v[3];
+            } else {
+                const auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, (int)off, 0, 0);
+                rows[u][0] = v[0]; rows[u][1] = v[1];
+            }
+        } else if constexpr (MODE == LOAD_WORD) {
+            constexpr int PER_WORD = 4 / T::BPC;
+#pragma unroll
+            for (int k = 0; k < T::LW; ++k) {
+                const int ik = i0 + k * PER_WORD;
+                const uint32_t off = ik < nin ? roff + (uint32_t)ik * T::BPC : OOB;
+                rows[u][k] = __builtin_amdgcn_raw_buffer_load_b32(rs, (int)off, 0, 0);
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < T::LW; ++k) {
+                uint32_t w = 0;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const int ib = i0 + (4 * k + c) / T::BPC;
+                    const uint32_t off = ib < nin ? roff + (uint32_t)(i0 * T::BPC + 4 * k + c) : OOB;
+                    w |= (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(rs, (int)off, 0, 0) << (8 * c);
+                }
+                rows[u][k] = w;
+            }
+        }
+    }
+}
+
+// Convert a task's rows to operand units and store them in LDS.
 template <int ACC, int IN, int TILE>
+__device__ __forceinline__ void stage_store(uint8_t *lds, int buf, int side, int tg, int chunk,
+                                            const uint32_t (&rows)[Tile<ACC, IN, TILE>::G][Tile<ACC, IN, TILE>::LW])
+{
+    using T = Tile<ACC, IN, TILE>;
+    uint8_t *base = lds + buf * 2 * T::SIDE_BYTES;
+    if constexpr (ACC == ACC_F16 && IN == IN_CI8) {
+        // unit of input e: word u = (fp16 re, fp16 im) of row u
+        uint32_t u[T::CI][4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int k = 0; k < T::LW; ++k) ci8x2_to_f16(rows[r][k], u[2 * k][r], u[2 * k + 1][r]);
+#pragma unroll
+        for (int e = 0; e < T::CI; ++e) {
+            const uint4 v = {u[e][0], u[e][1], u[e][2], u[e][3]};
+            *(uint4 *)(base + lds_off<ACC, IN, TILE>(side, tg, 0, chunk * T::CI + e)) = v;
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < T::CI; ++e) {
+            uint32_t u[T::WORDS];
+            if constexpr (ACC == ACC_I8) {
+                if constexpr (IN == IN_CI8) {
+                    const uint32_t sel = (e & 1) ? 0x07060302u : 0x05040100u;
+#pragma unroll
+                    for (int m = 0; m < 4; ++m)
+                        u[m] = __builtin_amdgcn_perm(rows[2 * m + 1][e >> 1], rows[2 * m][e >> 1], sel);
+                } else {
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) {
+                        int r0, i0, r1, i1;
+                        pair_of<IN>(rows[2 * m], e, r0, i0);
+                        pair_of<IN>(rows[2 * m + 1], e, r1, i1);
+                        u[m] = (uint32_t)(r0 & 0xFF) | ((uint32_t)(i0 & 0xFF) << 8) |
+                               ((uint32_t)(r1 & 0xFF) << 16) | ((uint32_t)(i1 & 0xFF) << 24);
+                    }
+                }
+            } else if constexpr (ACC == ACC_F16) {
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    int re, im;
+                    pair_of<IN>(rows[m], e, re, im);
+                    u[m] = f16_bits(re) | (f16_bits(im) << 16);
+                }
+            } else {
+#pragma unroll
+                for (int m = 0; m < 8; ++m) {
+                    int r0, i0, r1, i1;
+                    pair_of<IN>(rows[2 * m], e, r0, i0);
+                    pair_of<IN>(rows[2 * m + 1], e, r1, i1);
+                    uint32_t w = __builtin_amdgcn_cvt_pk_fp8_f32((float)r0, (float)i0, 0, false);
+                    u[m] = __builtin_amdgcn_cvt_pk_fp8_f32((float)r1, (float)i1, w, true);
+                }
+            }
+#pragma unroll
+            for (int pl = 0; pl < T::PLANES; ++pl) {
+                const uint4 v = {u[4 * pl], u[4 * pl + 1], u[4 * pl + 2], u[4 * pl + 3]};
+                *(uint4 *)(base + lds_off<ACC, IN, TILE>(side, tg, pl, chunk * T::CI + e)) = v;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- MAC loop over one block
+
+// One staged block: K-steps of 2G samples.  With two 32x32 blocks per wave side the wave
+// computes blocks (0,0), (1,0), (1,1) and, unless it sits on the diagonal of a diagonal
+// tile, block (0,1); the condition is wave-uniform, so the accumulators keep one register
+// assignment and only a scalar branch guards the last pair of MFMAs.
+template <int ACC, int IN, int TILE>
+__device__ __forceinline__ void mac_block(const uint8_t *base, int col_side, int wr, int wc, int lane, bool do01,
+                                          typename Tile<ACC, IN, TILE>::acc_t (&re)[Tile<ACC, IN, TILE>::NB][Tile<ACC, IN, TILE>::NB],
+                                          typename Tile<ACC, IN, TILE>::acc_t (&im)[Tile<ACC, IN, TILE>::NB][Tile<ACC, IN, TILE>::NB])
+{
+    using T = Tile<ACC, IN, TILE>;
+    constexpr int NB = T::NB;
+    const int r32 = lane & 31, half = lane >> 5;
+#pragma unroll
+    for (int s = 0; s < T::NTG / 2; ++s) {
+        const int tgk = 2 * s + half;
+        Frag<T::WORDS> A[NB], B[NB], C[NB];
+#pragma unroll
+        for (int a = 0; a < NB; ++a) {
+            const int row = (wr * NB + a) * 32 + r32;
+#pragma unroll
+            for (int pl = 0; pl < T::PLANES; ++pl) {
+                const uint4 v = *(const uint4 *)(base + lds_off<ACC, IN, TILE>(0, tgk, pl, row));
+                A[a].w[4 * pl] = v.x; A[a].w[4 * pl + 1] = v.y;
+                A[a].w[4 * pl + 2] = v.z; A[a].w[4 * pl + 3] = v.w;
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int col = (wc * NB + b) * 32 + r32;
+#pragma unroll
+            for (int pl = 0; pl < T::PLANES; ++pl) {
+                const uint4 v = *(const uint4 *)(base + lds_off<ACC, IN, TILE>(col_side, tgk, pl, col));
+                B[b].w[4 * pl] = v.x; B[b].w[4 * pl + 1] = v.y;
+                B[b].w[4 * pl + 2] = v.z; B[b].w[4 * pl + 3] = v.w;
+            }
+#pragma unroll
+            for (int k = 0; k < T::WORDS; ++k) C[b].w[k] = rotate_pairs<ACC>(B[b].w[k]);
+        }
+        mma(re[0][0], A[0], B[0]);
+        mma(im[0][0], A[0], C[0]);
+        if constexpr (NB == 2) {
+            mma(re[1][0], A[1], B[0]);
+            mma(im[1][0], A[1], C[0]);
+            mma(re[1][1], A[1], B[1]);
+            mma(im[1][1], A[1], C[1]);
+            if (do01) {
+                mma(re[0][1], A[0], B[1]);
+                mma(im[0][1], A[0], C[1]);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- epilogue
+
+__device__ __forceinline__ float swap_pair_lanes(float v)
+{
+    // lanes 2k and 2k+1 exchange values (quad_perm 1,0,3,2)
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0xB1, 0xF, 0xF, false));
+}
+__device__ __forceinline__ int swap_pair_lanes(int v) { return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false); }
+
+template <int ACC, int IN, int TILE>
+__device__ __forceinline__ void store_tile(const XJob &p, int f, int row0, int col0, int wr, int wc, int lane,
+                                           int mask,
+                                           typename Tile<ACC, IN, TILE>::acc_t (&re)[Tile<ACC, IN, TILE>::NB][Tile<ACC, IN, TILE>::NB],
+                                           typename Tile<ACC, IN, TILE>::acc_t (&im)[Tile<ACC, IN, TILE>::NB][Tile<ACC, IN, TILE>::NB])
+{
+    using T = Tile<ACC, IN, TILE>;
+    constexpr int NB = T::NB;
+    using val_t = typename std::conditional<ACC == ACC_I8, int, float>::type;
+    const int r32 = lane & 31, half = lane >> 5;
+    const int npol = p.npol;
+    const int64_t nbl = (int64_t)(p.nin / npol) * (p.nin / npol + 1) / 2;
+    if (npol == 2 && !p.accumulate) {
+        // Lanes 2k, 2k+1 hold columns q = 0, 1 of one station s2; registers k, k+1 hold
+        // rows p = 0, 1 of one station s1.  After one exchange each lane stores 16 bytes:
+        // the even lane the slots (0,0), (0,1), the odd lane the slots (1,0), (1,1).
+        const bool odd = lane & 1;
+#pragma unroll
+        for (int a = 0; a < NB; ++a)
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                if (!((mask >> (a * NB + b)) & 1)) continue;
+                const int j = col0 + (wc * NB + b) * 32 + r32;
+                const int s2 = j >> 1;
+#pragma unroll
+                for (int k = 0; k < 16; k += 2) {
+                    const int i = row0 + (wr * NB + a) * 32 + 8 * (k >> 2) + 4 * half + (k & 3);
+                    const int s1 = i >> 1;
+                    const val_t r0 = (val_t)re[a][b][k], r1 = (val_t)re[a][b][k + 1];
+                    const val_t m0 = (val_t)im[a][b][k], m1 = (val_t)im[a][b][k + 1];
+                    const val_t xr = swap_pair_lanes(odd ? r0 : r1);
+                    const val_t xm = swap_pair_lanes(odd ? m0 : m1);
+                    if (i >= p.nin || j >= p.nin || s1 < s2) continue;
+                    const int64_t o = ((int64_t)f * nbl + (int64_t)s1 * (s1 + 1) / 2 + s2) * 8 + (odd ? 4 : 0);
+                    if constexpr (ACC == ACC_I8) {
+                        const i32x4v v = odd ? (i32x4v){xr, xm, r1, m1} : (i32x4v){r0, m0, xr, xm};
+                        __builtin_nontemporal_store(v, (i32x4v *)((int *)p.out + o));
+                    } else {
+                        const f32x4 v = odd ? (f32x4){xr, xm, r1, m1} : (f32x4){r0, m0, xr, xm};
+                        __builtin_nontemporal_store(v, (f32x4 *)((float *)p.out + o));
+                    }
+                }
+            }
+        return;
+    }
+    const int npp = npol * npol;
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            if (!((mask >> (a * NB + b)) & 1)) continue;
+            const int j = col0 + (wc * NB + b) * 32 + r32;
+            if (j >= p.nin) continue;
+            const int s2 = j / npol, q = j - s2 * npol;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const int i = row0 + (wr * NB + a) * 32 + 8 * (k >> 2) + 4 * half + (k & 3);
+                if (i >= p.nin) continue;
+                const int s1 = i / npol, pp = i - s1 * npol;
+                if (s1 < s2) continue;
+                const int64_t o = (((int64_t)f * nbl + (int64_t)s1 * (s1 + 1) / 2 + s2) * npp + pp * npol + q) * 2;
+                if constexpr (ACC == ACC_I8) {
+                    if (p.accumulate) {
+                        unsigned long long *out = (unsigned long long *)p.out;
+                        atomicAdd(&out[o], (unsigned long long)(long long)re[a][b][k]);
+                        atomicAdd(&out[o + 1], (unsigned long long)(long long)im[a][b][k]);
+                    } else {
+                        *(int2 *)((int *)p.out + o) = make_int2(re[a][b][k], im[a][b][k]);
+                    }
+                } else {
+                    if (p.accumulate) {
+                        double *out = (double *)p.out;
+                        atomicAdd(&out[o], (double)re[a][b][k]);
+                        atomicAdd(&out[o + 1], (double)im[a][b][k]);
+                    } else {
+                        *(float2 *)((float *)p.out + o) = make_float2(re[a][b][k], im[a][b][k]);
+                    }
+                }
+            }
+        }
+}
+
+// ---------------------------------------------------------------- one work item
+
+template <int ACC, int IN, int TILE, int MODE>
 __device__ __forceinline__ void process_item(const XJob &p, int f, int g, int w, uint8_t *lds)
 {
     using T = Tile<ACC, IN, TILE>;
     using acc_t = typename T::acc_t;
     constexpr int NB = T::NB;
+    g = __builtin_amdgcn_readfirstlane(g);
+    w = __builtin_amdgcn_readfirstlane(w);
 
     // Triangular tile index -> (bx, by), bx <= by (Sec. 4.2), exact integer fix-up.
     int by = (int)((sqrtf(8.0f * (float)g + 1.0f) - 1.0f) * 0.5f);
@@ -274,26 +514,30 @@ __device__ __forceinline__ void process_item(const XJob &p, int f, int g, int w,
     const int bx = g - by * (by + 1) / 2;
     const bool diag = (bx == by);
     const int row0 = by * TILE, col0 = bx * TILE;
-    const int t_begin = w * p.window;
-    const int t_end = min(p.ntime, t_begin + p.window);
+    // item coordinates are wave-uniform: keep them (and the descriptors built from them)
+    // in scalar registers
+    f = __builtin_amdgcn_readfirstlane(f);
+    const int t_begin = __builtin_amdgcn_readfirstlane(w * p.window);
+    const int t_end = __builtin_amdgcn_readfirstlane(min(p.ntime, t_begin + p.window));
     const int nblk = (t_end - t_begin + T::TB - 1) / T::TB;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int wave = tid >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wr = wave >> 1, wc = wave & 1;
 
-    // Which 32x32 blocks of this wave are computed.
-    bool on[NB][NB];
-    bool any = false;
+    // 32x32 blocks this wave computes (wave-uniform): skip blocks strictly above the
+    // diagonal of a diagonal tile and blocks that start beyond the last input.
+    int mask = 0;
 #pragma unroll
     for (int a = 0; a < NB; ++a)
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
             const int rbi = wr * NB + a, cbi = wc * NB + b;
-            on[a][b] = !(diag && rbi < cbi) && (row0 + rbi * 32 < p.nin) && (col0 + cbi * 32 < p.nin);
-            any |= on[a][b];
+            if (!(diag && rbi < cbi) && row0 + rbi * 32 < p.nin && col0 + cbi * 32 < p.nin)
+                mask |= 1 << (a * NB + b);
         }
+    mask = __builtin_amdgcn_readfirstlane(mask);
 
     acc_t re[NB][NB], im[NB][NB];
 #pragma unroll
@@ -304,127 +548,68 @@ __device__ __forceinline__ void process_item(const XJob &p, int f, int g, int w,
             im[a][b] = (acc_t){};
         }
 
-    // Staging task of this thread: side, time group, input chunk.
+    // Staging task of this thread: side, time group, input chunk.  A diagonal tile stages
+    // one side; its spare threads repeat a task (same loads, same LDS values).
     const int nsides = diag ? 1 : 2;
-    const bool has_task = tid < nsides * T::NT;
-    const int side = tid / T::NT;
-    const int task = tid - side * T::NT;
+    const int tix = tid % (nsides * T::NT);
+    const int side = tix / T::NT;
+    const int task = tix - side * T::NT;
     const int tg = task % T::NTG;
     const int chunk = task / T::NTG;
-    const int side_row0 = side == 0 ? row0 : col0;
-    uint32_t rows[T::G][T::LW];
+    const int i0 = (side == 0 ? row0 : col0) + chunk * T::CI;
+    const uint32_t row_stride = (uint32_t)((int64_t)p.nchan * p.nin * T::BPC);
+    using rows_t = uint32_t[T::G][T::LW];
+    rows_t ra, rb;
 
-    auto stage_store = [&](int buf) {
-        if (!has_task) return;
-        uint8_t *base = lds + buf * 2 * T::SIDE_BYTES;
-#pragma unroll
-        for (int e = 0; e < T::CI; ++e) {
-            uint32_t u[T::WORDS];
-            pack_unit<ACC, IN, TILE>(rows, e, u);
-#pragma unroll
-            for (int pl = 0; pl < T::PLANES; ++pl) {
-                uint4 v = {u[4 * pl], u[4 * pl + 1], u[4 * pl + 2], u[4 * pl + 3]};
-                *(uint4 *)(base + lds_off<ACC, IN, TILE>(side, tg, pl, chunk * T::CI + e)) = v;
-            }
-        }
+    // Loads past the last block read nothing (empty descriptor) and are issued anyway, so
+    // the loop carries no branches between a load and the use of its registers.
+    const BlockRsrc brs(p, f, t_begin, t_end, T::TB, T::BPC);
+    auto load = [&](rows_t &rows, int blk) {
+        load_rows<ACC, IN, TILE, MODE>(brs.get(blk), row_stride, tg * T::G, i0, p.nin, rows);
+    };
+    auto stage = [&](const rows_t &rows, int buf) { stage_store<ACC, IN, TILE>(lds, buf, side, tg, chunk, rows); };
+    const int col_side = diag ? 0 : 1;
+    // Any wave with a block to store computes (0,0), (1,0), (1,1), and (0,1) unless the
+    // mask is the diagonal pattern; blocks of zero padding are computed but not stored.
+    const bool active = mask != 0;
+    const bool do01 = mask != T::DIAG;
+    auto compute = [&](int buf) {
+        if (active)
+            mac_block<ACC, IN, TILE>(lds + buf * 2 * T::SIDE_BYTES, col_side, wr, wc, lane, do01, re, im);
     };
 
-    if (has_task) load_task<ACC, IN, TILE>(p, f, side_row0, t_begin, t_end, tg, chunk, rows);
-    stage_store(0);
-    __syncthreads();
-
-    const int col_side = diag ? 0 : 1;
-    const int r32 = lane & 31, half = lane >> 5;
-
-    for (int blk = 0; blk < nblk; ++blk) {
-        const int cur = blk & 1;
-        const bool next = blk + 1 < nblk;
-        if (next && has_task)
-            load_task<ACC, IN, TILE>(p, f, side_row0, t_begin + (blk + 1) * T::TB, t_end, tg,
-                                     chunk, rows);
-        if (any) {
-            const uint8_t *base = lds + cur * 2 * T::SIDE_BYTES;
-#pragma unroll
-            for (int s = 0; s < T::NTG / 2; ++s) {
-                const int tgk = 2 * s + half;
-                Frag<T::WORDS> A[NB], B[NB], C[NB];
-#pragma unroll
-                for (int a = 0; a < NB; ++a) {
-                    const int row = (wr * NB + a) * 32 + r32;
-#pragma unroll
-                    for (int pl = 0; pl < T::PLANES; ++pl) {
-                        const uint4 v = *(const uint4 *)(base + lds_off<ACC, IN, TILE>(0, tgk, pl, row));
-                        A[a].w[4 * pl] = v.x; A[a].w[4 * pl + 1] = v.y;
-                        A[a].w[4 * pl + 2] = v.z; A[a].w[4 * pl + 3] = v.w;
-                    }
-                }
-#pragma unroll
-                for (int b = 0; b < NB; ++b) {
-                    const int col = (wc * NB + b) * 32 + r32;
-#pragma unroll
-                    for (int pl = 0; pl < T::PLANES; ++pl) {
-                        const uint4 v = *(const uint4 *)(base + lds_off<ACC, IN, TILE>(col_side, tgk, pl, col));
-                        B[b].w[4 * pl] = v.x; B[b].w[4 * pl + 1] = v.y;
-                        B[b].w[4 * pl + 2] = v.z; B[b].w[4 * pl + 3] = v.w;
-                    }
-#pragma unroll
-                    for (int k = 0; k < T::WORDS; ++k) C[b].w[k] = rotate_pairs<ACC>(B[b].w[k]);
-                }
-#pragma unroll
-                for (int a = 0; a < NB; ++a)
-#pragma unroll
-                    for (int b = 0; b < NB; ++b)
-                        if (on[a][b]) {
-                            mma(re[a][b], A[a], B[b]);
-                            mma(im[a][b], A[a], C[b]);
-                        }
-            }
-        }
-        if (next) stage_store(cur ^ 1);
+    if constexpr (T::DEPTH == 2) {
+        // Two register slots: block b+2 is loaded while block b is multiplied and block
+        // b+1 (loaded one step earlier) is converted into the other LDS buffer.
+        load(ra, 0);
+        load(rb, 1);
+        stage(ra, 0);
         __syncthreads();
+        for (int blk = 0; blk < nblk; blk += 2) {
+            load(ra, blk + 2);
+            compute(0);
+            stage(rb, 1);
+            __syncthreads();
+            if (blk + 1 >= nblk) break;
+            load(rb, blk + 3);
+            compute(1);
+            stage(ra, 0);
+            __syncthreads();
+        }
+    } else {
+        // One register slot: block b+1 is loaded while block b is multiplied.
+        load(ra, 0);
+        stage(ra, 0);
+        __syncthreads();
+        for (int blk = 0; blk < nblk; ++blk) {
+            load(ra, blk + 1);
+            compute(blk & 1);
+            stage(ra, (blk + 1) & 1);
+            __syncthreads();
+        }
     }
 
-    // Epilogue: lane holds column r32 of each block, rows 8*(k/4) + 4*half + k%4.
-    const int npol = p.npol;
-    const int64_t nbl = (int64_t)(p.nin / npol) * (p.nin / npol + 1) / 2;
-    const int npp = npol * npol;
-#pragma unroll
-    for (int a = 0; a < NB; ++a)
-#pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            if (!on[a][b]) continue;
-            const int j = col0 + (wc * NB + b) * 32 + r32;
-            if (j >= p.nin) continue;
-            const int s2 = j / npol, q = j - s2 * npol;
-#pragma unroll
-            for (int k = 0; k < 16; ++k) {
-                const int i = row0 + (wr * NB + a) * 32 + 8 * (k >> 2) + 4 * half + (k & 3);
-                if (i >= p.nin) continue;
-                const int s1 = i / npol, pp = i - s1 * npol;
-                if (s1 < s2) continue;
-                const int64_t o = (((int64_t)f * nbl + (int64_t)s1 * (s1 + 1) / 2 + s2) * npp +
-                                   pp * npol + q) * 2;
-                if constexpr (ACC == ACC_I8) {
-                    if (p.accumulate) {
-                        long long *out = (long long *)p.out;
-                        atomicAdd((unsigned long long *)&out[o], (unsigned long long)(long long)re[a][b][k]);
-                        atomicAdd((unsigned long long *)&out[o + 1], (unsigned long long)(long long)im[a][b][k]);
-                    } else {
-                        int2 v = {re[a][b][k], im[a][b][k]};
-                        *(int2 *)((int *)p.out + o) = v;
-                    }
-                } else {
-                    if (p.accumulate) {
-                        double *out = (double *)p.out;
-                        atomicAdd(&out[o], (double)re[a][b][k]);
-                        atomicAdd(&out[o + 1], (double)im[a][b][k]);
-                    } else {
-                        float2 v = {re[a][b][k], im[a][b][k]};
-                        *(float2 *)((float *)p.out + o) = v;
-                    }
-                }
-            }
-        }
+    store_tile<ACC, IN, TILE>(p, f, row0, col0, wr, wc, lane, mask, re, im);
 }
 
 // Item b of a single job -> (channel, tile, window).  With xcd_group 8, the workgroups of
@@ -449,13 +634,13 @@ __device__ __forceinline__ bool decode_item(const XJob &p, int64_t b, int &f, in
     return true;
 }
 
-template <int ACC, int IN, int TILE>
+template <int ACC, int IN, int TILE, int MODE>
 __global__ __launch_bounds__(NTHREADS, 2) void xeng_mfma_kernel(XJob p)
 {
     __shared__ __attribute__((aligned(16))) uint8_t lds[Tile<ACC, IN, TILE>::LDS_BYTES];
     int f, g, w;
     if (!decode_item(p, p.block0 + blockIdx.x, f, g, w)) return;
-    process_item<ACC, IN, TILE>(p, f, g, w, lds);
+    process_item<ACC, IN, TILE, MODE>(p, f, g, w, lds);
 }
 
 // Persistent batched kernel: workgroups take (job, channel, tile, window) items off a
@@ -474,15 +659,22 @@ __global__ __launch_bounds__(NTHREADS, 2) void xeng_mfma_batch_kernel(const XJob
         if (it >= nitems) break;
         const XItem item = items[it];
         const XJob p = jobs[item.job];
-        process_item<ACC, IN, TILE>(p, item.chan, item.tile, item.window, lds);
+        if (p.load_mode == LOAD_VEC) process_item<ACC, IN, TILE, LOAD_VEC>(p, item.chan, item.tile, item.window, lds);
+        else if (p.load_mode == LOAD_WORD) process_item<ACC, IN, TILE, LOAD_WORD>(p, item.chan, item.tile, item.window, lds);
+        else process_item<ACC, IN, TILE, LOAD_ELEM>(p, item.chan, item.tile, item.window, lds);
     }
 }
 
 template <int ACC, int IN, int TILE>
 int launch_one(const XJob &job, hipStream_t stream)
 {
-    hipLaunchKernelGGL((xeng_mfma_kernel<ACC, IN, TILE>), dim3((unsigned)job.grid), dim3(NTHREADS), 0,
-                       stream, job);
+    const dim3 grid((unsigned)job.grid), block(NTHREADS);
+    if (job.load_mode == LOAD_VEC)
+        hipLaunchKernelGGL((xeng_mfma_kernel<ACC, IN, TILE, LOAD_VEC>), grid, block, 0, stream, job);
+    else if (job.load_mode == LOAD_WORD)
+        hipLaunchKernelGGL((xeng_mfma_kernel<ACC, IN, TILE, LOAD_WORD>), grid, block, 0, stream, job);
+    else
+        hipLaunchKernelGGL((xeng_mfma_kernel<ACC, IN, TILE, LOAD_ELEM>), grid, block, 0, stream, job);
     return (int)hipGetLastError();
 }
 
