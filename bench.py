@@ -27,7 +27,7 @@ WORKLOAD = {
     "nstation": 128, "npol": 2, "nchan": 1024, "ntime": 1000,
     "dist": ("gauss", 3.0, 127), "seed_index": 1,
 }
-PEAK_TFLOPS = {"f16": 2500.0, "i8": 5000.0, "f8": 5000.0, "f32": 78.6}
+PEAK_TFLOPS = {"f16": 2500.0, "i8": 5000.0, "f8": 5000.0, "f32": 157.3}
 HBM_PEAK_GBPS = 8000.0
 
 
@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
     ap.add_argument("--only", default=None, help="time only this path (for profiling runs)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one device copy of 1 GiB (reference for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -115,6 +117,14 @@ def main():
             ref = v
         else:
             assert torch.equal(ref, v), f"path {p} disagrees with {list(outs)[0]}"
+
+    if args.calibrate_copy:
+        src = torch.empty(1 << 30, dtype=torch.uint8, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     head = "f16" if "f16" in results else paths[0]
     hr = results[head]

@@ -22,7 +22,7 @@ SOURCES = ["api.cpp", "plan.cpp", "xeng_mfma.hip", "xeng_cmac.hip", "xeng_util.h
 ARCH = "gfx950"
 # Packed FP32 VALU instructions are switched off for all device code.
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-munsafe-fp-atomics"]
-COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", f"-I{INCLUDE}", f"-I{CSRC}",
+COMMON = ["-O3", "-std=c++20", "-fPIC", f"--offload-arch={ARCH}", f"-I{INCLUDE}", f"-I{CSRC}",
           "-Wall", "-Wno-unused-function", "-Wno-unknown-pragmas"]
 
 

@@ -26,6 +26,7 @@
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
+#include <utility>
 
 #include "xeng.h"
 
@@ -108,7 +109,11 @@ __device__ __forceinline__ uint32_t rotate_pairs<ACC_I8>(uint32_t w)
 template <>
 __device__ __forceinline__ uint32_t rotate_pairs<ACC_F16>(uint32_t w)
 {
-    return __builtin_amdgcn_perm(w, w, 0x01000302u) ^ 0x00008000u;
+    // (re, im) -> (-im, re): swapped halves times (-1, 1), exact
+    typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+    const h2 v = __builtin_bit_cast(h2, w);
+    const h2 r = __builtin_shufflevector(v, v, 1, 0) * (h2){(_Float16)(-1.0f), (_Float16)1.0f};
+    return __builtin_bit_cast(uint32_t, r);
 }
 
 template <>
@@ -179,13 +184,14 @@ struct Tile {
     static constexpr int WORDS = O::WORDS;
     static constexpr int PLANES = WORDS / 4;
     static constexpr int NTG = TB / G;                       // time groups per block
-    static constexpr int SWZ = (NTG < 8 ? NTG : 8) - 1;      // row swizzle mask
     static constexpr int BPC = InFmtT<IN>::BPC;
     static constexpr int CI = (ACC == ACC_F8 && IN == IN_CI8) ? 4 : 8;  // inputs per load
     static constexpr int LW = CI * BPC / 4;                  // words per row load
     static constexpr int NT = NTG * (TILE / CI);             // staging tasks per side
     static constexpr int NB = TILE / 64;                     // 32x32 blocks per wave side
-    static constexpr int SIDE_BYTES = NTG * PLANES * TILE * 16;
+    static constexpr int PAD = 16;                           // bytes after each time group
+    static constexpr int TG_BYTES = PLANES * TILE * 16 + PAD;
+    static constexpr int SIDE_BYTES = NTG * TG_BYTES;
     static constexpr int LDS_BYTES = 2 * 2 * SIDE_BYTES;     // 2 buffers x 2 sides
     static constexpr int FULL = (1 << (NB * NB)) - 1;        // every block of the wave
     static constexpr int DIAG = NB == 2 ? 0xD : 1;           // blocks (0,0), (1,0), (1,1)
@@ -194,12 +200,16 @@ struct Tile {
     static_assert(TB % (2 * G) == 0, "time block holds whole K-steps");
 };
 
+// LDS layout of one side of one buffer: per time group a 16-byte unit per input (and per
+// plane), then 16 bytes of padding.  The padding shifts consecutive time groups by four
+// banks, so the stores of a staging wave (eight time groups x two input chunks per 16
+// lanes) and the loads of an MFMA operand (sixteen consecutive inputs) hit 64 distinct
+// banks; unit addresses differ by compile-time constants across K-steps and units.
 template <int ACC, int IN, int TILE>
 __device__ __forceinline__ uint32_t lds_off(int side, int tg, int plane, int row)
 {
     using T = Tile<ACC, IN, TILE>;
-    return (uint32_t)(side * T::SIDE_BYTES +
-                      ((tg * T::PLANES + plane) * TILE + (row ^ (tg & T::SWZ))) * 16);
+    return (uint32_t)(side * T::SIDE_BYTES + tg * T::TG_BYTES + (plane * TILE + row) * 16);
 }
 
 // ---------------------------------------------------------------- staging
@@ -285,28 +295,31 @@ __device__ __forceinline__ void load_rows(__amdgpu_buffer_rsrc_t rs, uint32_t ro
     }
 }
 
-// Convert a task's rows to operand units and store them in LDS.
-template <int ACC, int IN, int TILE>
+// Convert units E0 .. E1-1 (inputs of the chunk) of a task's rows to operand units and
+// store them in LDS.
+template <int ACC, int IN, int TILE, int E0 = 0, int E1 = Tile<ACC, IN, TILE>::CI>
 __device__ __forceinline__ void stage_store(uint8_t *lds, int buf, int side, int tg, int chunk,
                                             const uint32_t (&rows)[Tile<ACC, IN, TILE>::G][Tile<ACC, IN, TILE>::LW])
 {
     using T = Tile<ACC, IN, TILE>;
     uint8_t *base = lds + buf * 2 * T::SIDE_BYTES;
     if constexpr (ACC == ACC_F16 && IN == IN_CI8) {
-        // unit of input e: word u = (fp16 re, fp16 im) of row u
-        uint32_t u[T::CI][4];
+        // unit of input e: word r = (fp16 re, fp16 im) of row r; row word k holds inputs
+        // 2k and 2k+1
+        static_assert(E0 % 2 == 0 && E1 % 2 == 0, "whole row words");
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
+        for (int k = E0 / 2; k < E1 / 2; ++k) {
+            uint32_t u0[4], u1[4];
 #pragma unroll
-            for (int k = 0; k < T::LW; ++k) ci8x2_to_f16(rows[r][k], u[2 * k][r], u[2 * k + 1][r]);
-#pragma unroll
-        for (int e = 0; e < T::CI; ++e) {
-            const uint4 v = {u[e][0], u[e][1], u[e][2], u[e][3]};
-            *(uint4 *)(base + lds_off<ACC, IN, TILE>(side, tg, 0, chunk * T::CI + e)) = v;
+            for (int r = 0; r < 4; ++r) ci8x2_to_f16(rows[r][k], u0[r], u1[r]);
+            const uint4 v0 = {u0[0], u0[1], u0[2], u0[3]};
+            const uint4 v1 = {u1[0], u1[1], u1[2], u1[3]};
+            *(uint4 *)(base + lds_off<ACC, IN, TILE>(side, tg, 0, chunk * T::CI + 2 * k)) = v0;
+            *(uint4 *)(base + lds_off<ACC, IN, TILE>(side, tg, 0, chunk * T::CI + 2 * k + 1)) = v1;
         }
     } else {
 #pragma unroll
-        for (int e = 0; e < T::CI; ++e) {
+        for (int e = E0; e < E1; ++e) {
             uint32_t u[T::WORDS];
             if constexpr (ACC == ACC_I8) {
                 if constexpr (IN == IN_CI8) {
@@ -356,6 +369,49 @@ __device__ __forceinline__ void stage_store(uint8_t *lds, int buf, int side, int
 // computes blocks (0,0), (1,0), (1,1) and, unless it sits on the diagonal of a diagonal
 // tile, block (0,1); the condition is wave-uniform, so the accumulators keep one register
 // assignment and only a scalar branch guards the last pair of MFMAs.
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    [&]<int... I>(std::integer_sequence<int, I...>) { (f(std::integral_constant<int, I>{}), ...); }(
+        std::make_integer_sequence<int, N>{});
+}
+
+// after(s) runs after the MFMAs of K-step s are issued: the caller converts and stores a
+// share of the next block there, so that its VALU work issues while the MFMAs execute.
+template <int ACC, int IN, int TILE>
+__device__ __forceinline__ void read_frags(const uint8_t *base, int col_side, int wr, int wc, int r32, int tgk,
+                                           Frag<Tile<ACC, IN, TILE>::WORDS> (&A)[Tile<ACC, IN, TILE>::NB],
+                                           Frag<Tile<ACC, IN, TILE>::WORDS> (&B)[Tile<ACC, IN, TILE>::NB])
+{
+    using T = Tile<ACC, IN, TILE>;
+    constexpr int NB = T::NB;
+#pragma unroll
+    for (int a = 0; a < NB; ++a) {
+        const int row = (wr * NB + a) * 32 + r32;
+#pragma unroll
+        for (int pl = 0; pl < T::PLANES; ++pl) {
+            const uint4 v = *(const uint4 *)(base + lds_off<ACC, IN, TILE>(0, tgk, pl, row));
+            A[a].w[4 * pl] = v.x; A[a].w[4 * pl + 1] = v.y;
+            A[a].w[4 * pl + 2] = v.z; A[a].w[4 * pl + 3] = v.w;
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const int col = (wc * NB + b) * 32 + r32;
+#pragma unroll
+        for (int pl = 0; pl < T::PLANES; ++pl) {
+            const uint4 v = *(const uint4 *)(base + lds_off<ACC, IN, TILE>(col_side, tgk, pl, col));
+            B[b].w[4 * pl] = v.x; B[b].w[4 * pl + 1] = v.y;
+            B[b].w[4 * pl + 2] = v.z; B[b].w[4 * pl + 3] = v.w;
+        }
+    }
+}
+
+// One staged block: K-steps of 2G samples, the operands of step s+1 read from LDS while
+// the MFMAs of step s run.  With two 32x32 blocks per wave side the wave computes blocks
+// (0,0), (1,0), (1,1) and, unless it sits on the diagonal of a diagonal tile, block (0,1);
+// the condition is wave-uniform, so the accumulators keep one register assignment and only
+// a scalar branch guards the last pair of MFMAs.
 template <int ACC, int IN, int TILE>
 __device__ __forceinline__ void mac_block(const uint8_t *base, int col_side, int wr, int wc, int lane, bool do01,
                                           typename Tile<ACC, IN, TILE>::acc_t (&re)[Tile<ACC, IN, TILE>::NB][Tile<ACC, IN, TILE>::NB],
@@ -363,46 +419,33 @@ __device__ __forceinline__ void mac_block(const uint8_t *base, int col_side, int
 {
     using T = Tile<ACC, IN, TILE>;
     constexpr int NB = T::NB;
+    constexpr int KSTEPS = T::NTG / 2;
     const int r32 = lane & 31, half = lane >> 5;
+    Frag<T::WORDS> A[2][NB], B[2][NB];
+    read_frags<ACC, IN, TILE>(base, col_side, wr, wc, r32, half, A[0], B[0]);
+    static_for<KSTEPS>([&](auto S) {
+        constexpr int s = decltype(S)::value;
+        constexpr int cur = s & 1;
+        if constexpr (s + 1 < KSTEPS)
+            read_frags<ACC, IN, TILE>(base, col_side, wr, wc, r32, 2 * (s + 1) + half, A[cur ^ 1], B[cur ^ 1]);
+        Frag<T::WORDS> C[NB];
 #pragma unroll
-    for (int s = 0; s < T::NTG / 2; ++s) {
-        const int tgk = 2 * s + half;
-        Frag<T::WORDS> A[NB], B[NB], C[NB];
+        for (int b = 0; b < NB; ++b)
 #pragma unroll
-        for (int a = 0; a < NB; ++a) {
-            const int row = (wr * NB + a) * 32 + r32;
-#pragma unroll
-            for (int pl = 0; pl < T::PLANES; ++pl) {
-                const uint4 v = *(const uint4 *)(base + lds_off<ACC, IN, TILE>(0, tgk, pl, row));
-                A[a].w[4 * pl] = v.x; A[a].w[4 * pl + 1] = v.y;
-                A[a].w[4 * pl + 2] = v.z; A[a].w[4 * pl + 3] = v.w;
-            }
-        }
-#pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            const int col = (wc * NB + b) * 32 + r32;
-#pragma unroll
-            for (int pl = 0; pl < T::PLANES; ++pl) {
-                const uint4 v = *(const uint4 *)(base + lds_off<ACC, IN, TILE>(col_side, tgk, pl, col));
-                B[b].w[4 * pl] = v.x; B[b].w[4 * pl + 1] = v.y;
-                B[b].w[4 * pl + 2] = v.z; B[b].w[4 * pl + 3] = v.w;
-            }
-#pragma unroll
-            for (int k = 0; k < T::WORDS; ++k) C[b].w[k] = rotate_pairs<ACC>(B[b].w[k]);
-        }
-        mma(re[0][0], A[0], B[0]);
-        mma(im[0][0], A[0], C[0]);
+            for (int k = 0; k < T::WORDS; ++k) C[b].w[k] = rotate_pairs<ACC>(B[cur][b].w[k]);
+        mma(re[0][0], A[cur][0], B[cur][0]);
+        mma(im[0][0], A[cur][0], C[0]);
         if constexpr (NB == 2) {
-            mma(re[1][0], A[1], B[0]);
-            mma(im[1][0], A[1], C[0]);
-            mma(re[1][1], A[1], B[1]);
-            mma(im[1][1], A[1], C[1]);
+            mma(re[1][0], A[cur][1], B[cur][0]);
+            mma(im[1][0], A[cur][1], C[0]);
+            mma(re[1][1], A[cur][1], B[cur][1]);
+            mma(im[1][1], A[cur][1], C[1]);
             if (do01) {
-                mma(re[0][1], A[0], B[1]);
-                mma(im[0][1], A[0], C[1]);
+                mma(re[0][1], A[cur][0], B[cur][1]);
+                mma(im[0][1], A[cur][0], C[1]);
             }
         }
-    }
+    });
 }
 
 // ---------------------------------------------------------------- epilogue
@@ -573,9 +616,14 @@ __device__ __forceinline__ void process_item(const XJob &p, int f, int g, int w,
     // mask is the diagonal pattern; blocks of zero padding are computed but not stored.
     const bool active = mask != 0;
     const bool do01 = mask != T::DIAG;
-    auto compute = [&](int buf) {
+
+    // Multiply the block in LDS buffer `cur`, then convert `rows` (the next block) into
+    // buffer `cur ^ 1`.  (Converting a share after each K-step instead, so that the VALU
+    // work issues under the MFMAs, needs more registers than two waves per SIMD allow.)
+    auto step = [&](int cur, const rows_t &rows) {
         if (active)
-            mac_block<ACC, IN, TILE>(lds + buf * 2 * T::SIDE_BYTES, col_side, wr, wc, lane, do01, re, im);
+            mac_block<ACC, IN, TILE>(lds + cur * 2 * T::SIDE_BYTES, col_side, wr, wc, lane, do01, re, im);
+        stage(rows, cur ^ 1);
     };
 
     if constexpr (T::DEPTH == 2) {
@@ -587,24 +635,24 @@ __device__ __forceinline__ void process_item(const XJob &p, int f, int g, int w,
         __syncthreads();
         for (int blk = 0; blk < nblk; blk += 2) {
             load(ra, blk + 2);
-            compute(0);
-            stage(rb, 1);
+            step(0, rb);
             __syncthreads();
             if (blk + 1 >= nblk) break;
             load(rb, blk + 3);
-            compute(1);
-            stage(ra, 0);
+            step(1, ra);
             __syncthreads();
         }
     } else {
-        // One register slot: block b+1 is loaded while block b is multiplied.
+        // One register slot: block b+1 is loaded while block b is multiplied; it is
+        // converted after the last K-step.
         load(ra, 0);
         stage(ra, 0);
         __syncthreads();
         for (int blk = 0; blk < nblk; ++blk) {
             load(ra, blk + 1);
-            compute(blk & 1);
-            stage(ra, (blk + 1) & 1);
+            const int cur = blk & 1;
+            if (active) mac_block<ACC, IN, TILE>(lds + cur * 2 * T::SIDE_BYTES, col_side, wr, wc, lane, do01, re, im);
+            stage(ra, cur ^ 1);
             __syncthreads();
         }
     }
@@ -634,10 +682,12 @@ __device__ __forceinline__ bool decode_item(const XJob &p, int64_t b, int &f, in
     return true;
 }
 
+extern __shared__ __attribute__((aligned(16))) uint8_t dyn_lds[];
+
 template <int ACC, int IN, int TILE, int MODE>
 __global__ __launch_bounds__(NTHREADS, 2) void xeng_mfma_kernel(XJob p)
 {
-    __shared__ __attribute__((aligned(16))) uint8_t lds[Tile<ACC, IN, TILE>::LDS_BYTES];
+    uint8_t *lds = dyn_lds;
     int f, g, w;
     if (!decode_item(p, p.block0 + blockIdx.x, f, g, w)) return;
     process_item<ACC, IN, TILE, MODE>(p, f, g, w, lds);
@@ -649,7 +699,7 @@ template <int ACC, int IN, int TILE>
 __global__ __launch_bounds__(NTHREADS, 2) void xeng_mfma_batch_kernel(const XJob *jobs, const XItem *items,
                                                                       int64_t nitems, unsigned int *counter)
 {
-    __shared__ __attribute__((aligned(16))) uint8_t lds[Tile<ACC, IN, TILE>::LDS_BYTES];
+    uint8_t *lds = dyn_lds;
     __shared__ int64_t next;
     for (;;) {
         if (threadIdx.x == 0) next = (int64_t)atomicAdd(counter, 1u);
@@ -665,25 +715,45 @@ __global__ __launch_bounds__(NTHREADS, 2) void xeng_mfma_batch_kernel(const XJob
     }
 }
 
+// Kernels use more than the default 64 KiB of dynamic LDS; raise the limit once per kernel.
+template <typename K>
+int allow_lds(K kernel, int bytes)
+{
+    static int done = 0;  // one static per kernel instantiation
+    if (!done) {
+        const hipError_t e = hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        if (e != hipSuccess) return (int)e;
+        done = 1;
+    }
+    return 0;
+}
+
+template <int ACC, int IN, int TILE, int MODE>
+int launch_mode(const XJob &job, hipStream_t stream)
+{
+    constexpr int LDS = Tile<ACC, IN, TILE>::LDS_BYTES;
+    auto k = xeng_mfma_kernel<ACC, IN, TILE, MODE>;
+    if (int e = allow_lds(k, LDS)) return e;
+    hipLaunchKernelGGL(k, dim3((unsigned)job.grid), dim3(NTHREADS), LDS, stream, job);
+    return (int)hipGetLastError();
+}
+
 template <int ACC, int IN, int TILE>
 int launch_one(const XJob &job, hipStream_t stream)
 {
-    const dim3 grid((unsigned)job.grid), block(NTHREADS);
-    if (job.load_mode == LOAD_VEC)
-        hipLaunchKernelGGL((xeng_mfma_kernel<ACC, IN, TILE, LOAD_VEC>), grid, block, 0, stream, job);
-    else if (job.load_mode == LOAD_WORD)
-        hipLaunchKernelGGL((xeng_mfma_kernel<ACC, IN, TILE, LOAD_WORD>), grid, block, 0, stream, job);
-    else
-        hipLaunchKernelGGL((xeng_mfma_kernel<ACC, IN, TILE, LOAD_ELEM>), grid, block, 0, stream, job);
-    return (int)hipGetLastError();
+    if (job.load_mode == LOAD_VEC) return launch_mode<ACC, IN, TILE, LOAD_VEC>(job, stream);
+    if (job.load_mode == LOAD_WORD) return launch_mode<ACC, IN, TILE, LOAD_WORD>(job, stream);
+    return launch_mode<ACC, IN, TILE, LOAD_ELEM>(job, stream);
 }
 
 template <int ACC, int IN, int TILE>
 int launch_batch(const XJob *jobs, const XItem *items, int64_t nitems, unsigned int *counter,
                  int nblocks, hipStream_t stream)
 {
-    hipLaunchKernelGGL((xeng_mfma_batch_kernel<ACC, IN, TILE>), dim3(nblocks), dim3(NTHREADS), 0,
-                       stream, jobs, items, nitems, counter);
+    constexpr int LDS = Tile<ACC, IN, TILE>::LDS_BYTES;
+    auto k = xeng_mfma_batch_kernel<ACC, IN, TILE>;
+    if (int e = allow_lds(k, LDS)) return e;
+    hipLaunchKernelGGL(k, dim3(nblocks), dim3(NTHREADS), LDS, stream, jobs, items, nitems, counter);
     return (int)hipGetLastError();
 }
 
