@@ -45,8 +45,9 @@
  * sum of integers is exact, in any order); the wider accumulators of Sec. 2.3 then hold the
  * total.  A run of one window writes ci32 (int32 accumulators) or c64 (fp32 accumulators);
  * a run of several windows sums the windows on the GPU into ci64 or c128.  max_abs defaults
- * to 127 for CI8 and 8 for CI4; xcorr_set_max_abs declares a smaller bound on the data
- * (a promise by the caller, not checked).  CF32 input always runs one window and writes c64.
+ * to 127 for CI8 on the int8 path, 128 for CI8 on the other paths and 8 for CI4;
+ * xcorr_set_max_abs declares a smaller bound on the data (a promise by the caller, not
+ * checked).  CF32 input always runs one window and writes c64.
  *
  * Ownership and ordering.  Input and output are device pointers owned by the caller and
  * must stay valid until the work enqueued on `stream` has completed.  Every run is
@@ -105,8 +106,8 @@ typedef struct xcorr_handle xcorr_handle_t;
 
 /*
  * Plan a job of nstation stations x npol (1 or 2) polarisations, nchan channels and ntime
- * samples (the sizes of Eq. 4 and Algorithm 1).  Uploads the job's work list to the
- * current device.  Returns NULL on error.
+ * samples (the sizes of Eq. 4 and Algorithm 1) on the current device.  Allocates no device
+ * memory.  Returns NULL on error.
  */
 xcorr_handle_t *xcorr_create(int nstation, int npol, int nchan, int ntime,
                              xcorr_in_dtype in_dtype, xcorr_acc_dtype acc_dtype);
@@ -127,6 +128,85 @@ int xcorr_out_type(const xcorr_handle_t *h); /* an xcorr_out_dtype, or < 0 on er
 
 /* Text of the last error on the calling thread ("" if none). */
 const char *xcorr_last_error(void);
+
+/* ------------------------------------------------------------------ batches of jobs */
+
+/*
+ * Many independent jobs of different sizes (uneven sub-arrays, channel counts and
+ * integration lengths) in one persistent launch.  The increase of thread blocks with the
+ * number of channels is what keeps the GPU busy at small N (Sec. 6.1); a batch gets the
+ * same effect from many small jobs.  All jobs share the sample format and the arithmetic
+ * path; each job has its own input and output buffers with the layouts above.
+ */
+typedef struct {
+    int nstation;
+    int npol;
+    int nchan;
+    int ntime;
+} xcorr_job;
+
+typedef struct xcorr_batch xcorr_batch_t;
+
+/* Plan njobs jobs; uploads the work list (one item per job, channel, tile and window) to
+ * the current device.  Returns NULL on error. */
+xcorr_batch_t *xcorr_batch_create(int njobs, const xcorr_job *jobs, xcorr_in_dtype in_dtype,
+                                  xcorr_acc_dtype acc_dtype);
+
+/* Component bound for every job (as xcorr_set_max_abs); rebuilds the work list. */
+int xcorr_batch_set_max_abs(xcorr_batch_t *b, int max_abs);
+
+/* in[j], out[j]: device buffers of job j (host arrays of njobs device pointers).  Enqueues
+ * on `stream`: a small upload of the job table, the persistent kernel, and zero fills of
+ * the outputs that sum several windows.  May wait on the host for the previous run's
+ * table upload to finish. */
+int xcorr_batch_run(xcorr_batch_t *b, const void *const *in, void *const *out, hipStream_t stream);
+
+size_t xcorr_batch_in_bytes(const xcorr_batch_t *b, int job);
+size_t xcorr_batch_out_bytes(const xcorr_batch_t *b, int job);
+int xcorr_batch_out_type(const xcorr_batch_t *b, int job);
+int64_t xcorr_batch_items(const xcorr_batch_t *b);
+void xcorr_batch_destroy(xcorr_batch_t *b);
+
+/* ------------------------------------------------------------------ streaming integration */
+
+/*
+ * The integrated X-engine of Algorithm 1 (Sec. 5): the input of a long integration arrives
+ * from the host in chunks of chunk_ntime samples; chunk p+1 is copied to the device while
+ * chunk p is correlated, and every chunk's visibilities are added to running totals on the
+ * device.  The totals are always wide (ci64 for the int8 path, c128 otherwise) and exact:
+ * each chunk is integrated in exact windows (see above) and added to the totals in
+ * int64 / fp64.
+ *
+ * The stream owns a copy stream (default priority), two device chunk buffers and their
+ * events.  Host chunks should be pinned (hipHostMalloc) for the copies to be asynchronous;
+ * a chunk passed to xcorr_stream_push must stay unchanged until the push after next has
+ * returned or xcorr_stream_end has been called and `stream` synchronised.
+ */
+typedef struct xcorr_stream xcorr_stream_t;
+
+xcorr_stream_t *xcorr_stream_create(int nstation, int npol, int nchan, int chunk_ntime,
+                                    xcorr_in_dtype in_dtype, xcorr_acc_dtype acc_dtype);
+
+/* As xcorr_set_max_abs, for every chunk; call before xcorr_stream_begin. */
+int xcorr_stream_set_max_abs(xcorr_stream_t *s, int max_abs);
+
+/* Start an integration into `out` (device, xcorr_stream_out_bytes, type
+ * xcorr_stream_out_type): zero it on `stream`. */
+int xcorr_stream_begin(xcorr_stream_t *s, void *out, hipStream_t stream);
+
+/* Copy one chunk (host, xcorr_stream_chunk_bytes, layout [chunk_ntime][nchan][nstation][npol])
+ * to the device and add its visibilities to the totals; both steps are enqueued, ordered
+ * after earlier work on `stream`. */
+int xcorr_stream_push(xcorr_stream_t *s, const void *host_chunk, hipStream_t stream);
+
+/* Finish the integration: all of its work is ordered before later work on `stream`.
+ * Returns the number of samples integrated (>= 0) or an error code. */
+int64_t xcorr_stream_end(xcorr_stream_t *s, hipStream_t stream);
+
+size_t xcorr_stream_chunk_bytes(const xcorr_stream_t *s);
+size_t xcorr_stream_out_bytes(const xcorr_stream_t *s);
+int xcorr_stream_out_type(const xcorr_stream_t *s);
+void xcorr_stream_destroy(xcorr_stream_t *s);
 
 /* ------------------------------------------------------------------ host-only planning */
 

@@ -215,3 +215,399 @@ int xcorr_out_type(const xcorr_handle_t *h)
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------ batches
+
+struct xcorr_batch {
+    int device = 0;
+    int in_fmt = 0, acc = 0, tile = 0, mode = 0, nblocks = 0;
+    std::vector<xcorr_job> jobs;
+    std::vector<Plan> plans;
+    XQueues queues{};
+    int64_t nitems = 0;
+    XItem *items_dev = nullptr;
+    XJob *jobs_dev = nullptr;
+    XJob *jobs_pinned = nullptr;
+    unsigned int *counters_dev = nullptr;
+    hipEvent_t uploaded = nullptr;
+    bool upload_pending = false;
+};
+
+namespace {
+
+void batch_free(xcorr_batch *b)
+{
+    if (!b) return;
+    if (b->items_dev) (void)hipFree(b->items_dev);
+    if (b->jobs_dev) (void)hipFree(b->jobs_dev);
+    if (b->counters_dev) (void)hipFree(b->counters_dev);
+    if (b->jobs_pinned) (void)hipHostFree(b->jobs_pinned);
+    if (b->uploaded) (void)hipEventDestroy(b->uploaded);
+    delete b;
+}
+
+// Plan every job with a common tile and load mode, build the queues of work items and
+// upload them.  Items of one (job, channel) share a queue, so on the XCD that owns the
+// queue the tiles re-reading that channel's inputs share an L2; each queue is ordered
+// longest item first.
+int batch_plan(xcorr_batch *b, int max_abs)
+{
+    const int njobs = (int)b->jobs.size();
+    int max_nin = 0;
+    for (const xcorr_job &j : b->jobs) max_nin = std::max(max_nin, j.nstation * j.npol);
+    const int tile = b->acc == ACC_F32_CMAC ? 64 : (max_nin > 64 ? 128 : 64);
+    std::vector<Plan> plans(njobs);
+    std::string err;
+    int ci = b->acc == ACC_F32_CMAC ? 4 : ((b->acc == ACC_F8 && b->in_fmt == IN_CI8) ? 4 : 8);
+    int mode = LOAD_VEC;
+    for (int j = 0; j < njobs; ++j) {
+        const xcorr_job &jb = b->jobs[j];
+        int ma = max_abs;
+        if (b->acc == ACC_F8 && b->in_fmt == IN_CI8 && ma == 0) ma = 16;  // runs refused until declared
+        const int rc = make_plan(jb.nstation, jb.npol, jb.nchan, jb.ntime, b->in_fmt, b->acc, ma, tile, &plans[j], &err);
+        if (rc) return fail(rc, "job " + std::to_string(j) + ": " + err);
+        if (b->acc == ACC_F8 && b->in_fmt == IN_CI8 && max_abs == 0) plans[j].max_abs = 128;
+        mode = std::max(mode, load_mode_for(plans[j].nin, b->in_fmt, ci));
+        if (b->acc != ACC_F32_CMAC &&
+            64.0 * (double)jb.nchan * plans[j].nin * (double)in_sample_bytes(b->in_fmt) >= 4294901760.0)
+            return fail(XCORR_ERR_RANGE, "job " + std::to_string(j) + ": nchan * nin too large");
+    }
+    // work items with a cost estimate (computed pairs of the tile x samples of the window)
+    struct Cost {
+        double cost;
+        XItem it;
+    };
+    std::vector<std::vector<Cost>> q(NQUEUE);
+    for (int j = 0; j < njobs; ++j) {
+        const Plan &pl = plans[j];
+        for (int f = 0; f < pl.nchan; ++f) {
+            const int qq = (int)(((int64_t)j * 131 + f) % NQUEUE);
+            for (int w = 0; w < pl.nwindows; ++w) {
+                const int len = std::min(pl.ntime - w * pl.window, pl.window);
+                for (int g = 0; g < pl.tiles_per_chan; ++g) {
+                    int64_t bx, by;
+                    tile_coords(g, &bx, &by);
+                    const int rows = std::min(pl.tile, pl.nin - (int)by * pl.tile);
+                    const int cols = std::min(pl.tile, pl.nin - (int)bx * pl.tile);
+                    double c = (double)rows * cols * len;
+                    if (bx == by && b->acc != ACC_F32_CMAC) c *= 0.625;  // lower 32x32 blocks only
+                    q[qq].push_back({c, XItem{j, f, g, w}});
+                }
+            }
+        }
+    }
+    std::vector<XItem> items;
+    XQueues qs{};
+    for (int k = 0; k < NQUEUE; ++k) {
+        std::stable_sort(q[k].begin(), q[k].end(), [](const Cost &a, const Cost &c) { return a.cost > c.cost; });
+        qs.begin[k] = (int64_t)items.size();
+        for (const Cost &c : q[k]) items.push_back(c.it);
+        qs.end[k] = (int64_t)items.size();
+    }
+    if (b->items_dev) {
+        (void)hipFree(b->items_dev);
+        b->items_dev = nullptr;
+    }
+    if (!items.empty()) {
+        hipError_t e = hipMalloc(&b->items_dev, items.size() * sizeof(XItem));
+        if (e != hipSuccess) return hip_fail((int)e, "hipMalloc work list");
+        e = hipMemcpy(b->items_dev, items.data(), items.size() * sizeof(XItem), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail((int)e, "upload work list");
+    }
+    b->plans = plans;
+    b->tile = tile;
+    b->mode = mode;
+    b->queues = qs;
+    b->nitems = (int64_t)items.size();
+    const int cus = device_cus();
+    b->nblocks = std::max(1, cus) * (b->acc == ACC_F32_CMAC ? 4 : 2);
+    if ((int64_t)b->nblocks > b->nitems) b->nblocks = (int)std::max<int64_t>(1, b->nitems);
+    return XCORR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+xcorr_batch_t *xcorr_batch_create(int njobs, const xcorr_job *jobs, xcorr_in_dtype in_dtype,
+                                  xcorr_acc_dtype acc_dtype)
+{
+    if (njobs < 1 || !jobs) {
+        fail(XCORR_ERR_INVALID_ARG, "need njobs >= 1 and a job array");
+        return nullptr;
+    }
+    xcorr_batch *b = new (std::nothrow) xcorr_batch;
+    if (!b) {
+        fail(XCORR_ERR_OOM, "host allocation");
+        return nullptr;
+    }
+    b->in_fmt = (int)in_dtype;
+    b->acc = (int)acc_dtype;
+    b->jobs.assign(jobs, jobs + njobs);
+    hipError_t e = hipGetDevice(&b->device);
+    if (e != hipSuccess) {
+        hip_fail((int)e, "hipGetDevice");
+        batch_free(b);
+        return nullptr;
+    }
+    if (batch_plan(b, 0) != XCORR_OK) {
+        batch_free(b);
+        return nullptr;
+    }
+    if ((e = hipMalloc(&b->jobs_dev, njobs * sizeof(XJob))) != hipSuccess ||
+        (e = hipMalloc(&b->counters_dev, NQUEUE * COUNTER_STRIDE * sizeof(unsigned int))) != hipSuccess ||
+        (e = hipHostMalloc(&b->jobs_pinned, njobs * sizeof(XJob), hipHostMallocDefault)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&b->uploaded, hipEventDisableTiming)) != hipSuccess) {
+        hip_fail((int)e, "batch allocation");
+        batch_free(b);
+        return nullptr;
+    }
+    return b;
+}
+
+int xcorr_batch_set_max_abs(xcorr_batch_t *b, int max_abs)
+{
+    if (!b) return fail(XCORR_ERR_INVALID_ARG, "null batch");
+    if (b->in_fmt == IN_CF32) return fail(XCORR_ERR_INVALID_ARG, "max_abs applies to integer samples");
+    if (max_abs < 1) return fail(XCORR_ERR_INVALID_ARG, "max_abs must be >= 1");
+    return batch_plan(b, max_abs);
+}
+
+int xcorr_batch_run(xcorr_batch_t *b, const void *const *in, void *const *out, hipStream_t stream)
+{
+    if (!b || !in || !out) return fail(XCORR_ERR_INVALID_ARG, "null batch or pointer array");
+    const int njobs = (int)b->jobs.size();
+    if (b->acc == ACC_F8 && b->in_fmt == IN_CI8 && b->plans[0].max_abs > 16)
+        return fail(XCORR_ERR_UNSUPPORTED, "fp8 e4m3 needs max_abs <= 16 (call xcorr_batch_set_max_abs)");
+    for (int j = 0; j < njobs; ++j)
+        if (!out[j] || (!in[j] && b->plans[j].ntime > 0))
+            return fail(XCORR_ERR_INVALID_ARG, "null input or output of job " + std::to_string(j));
+    hipError_t e;
+    if (b->upload_pending) {
+        // the pinned table is still being read by the previous run's copy
+        if ((e = hipEventSynchronize(b->uploaded)) != hipSuccess) return hip_fail((int)e, "batch table event");
+        b->upload_pending = false;
+    }
+    for (int j = 0; j < njobs; ++j) {
+        XJob jb = job_from_plan(b->plans[j], in[j], out[j]);
+        jb.load_mode = b->mode;
+        b->jobs_pinned[j] = jb;
+    }
+    if ((e = hipMemcpyAsync(b->jobs_dev, b->jobs_pinned, njobs * sizeof(XJob), hipMemcpyHostToDevice, stream)) !=
+        hipSuccess)
+        return hip_fail((int)e, "batch table upload");
+    if ((e = hipEventRecord(b->uploaded, stream)) != hipSuccess) return hip_fail((int)e, "batch table event");
+    b->upload_pending = true;
+    int rc = launch_zero(b->counters_dev, NQUEUE * COUNTER_STRIDE * sizeof(unsigned int), stream);
+    if (rc) return hip_fail(rc, "zero counters");
+    for (int j = 0; j < njobs; ++j)
+        if (b->plans[j].nwindows != 1) {
+            rc = launch_zero(out[j], b->plans[j].out_bytes, stream);
+            if (rc) return hip_fail(rc, "zero fill");
+        }
+    if (b->nitems == 0) return XCORR_OK;
+    rc = b->acc == ACC_F32_CMAC
+             ? launch_cmac_batch(b->jobs_dev, b->items_dev, b->queues, b->counters_dev, b->in_fmt, b->nblocks, stream)
+             : launch_mfma_batch(b->jobs_dev, b->items_dev, b->queues, b->counters_dev, b->acc, b->in_fmt, b->tile,
+                                 b->mode, b->nblocks, stream);
+    if (rc) return hip_fail(rc, "batch kernel launch");
+    return XCORR_OK;
+}
+
+size_t xcorr_batch_in_bytes(const xcorr_batch_t *b, int job)
+{
+    return (b && job >= 0 && job < (int)b->plans.size()) ? b->plans[job].in_bytes : 0;
+}
+
+size_t xcorr_batch_out_bytes(const xcorr_batch_t *b, int job)
+{
+    return (b && job >= 0 && job < (int)b->plans.size()) ? b->plans[job].out_bytes : 0;
+}
+
+int xcorr_batch_out_type(const xcorr_batch_t *b, int job)
+{
+    if (!b || job < 0 || job >= (int)b->plans.size()) return fail(XCORR_ERR_INVALID_ARG, "bad batch or job");
+    return b->plans[job].out_dtype;
+}
+
+int64_t xcorr_batch_items(const xcorr_batch_t *b) { return b ? b->nitems : 0; }
+
+void xcorr_batch_destroy(xcorr_batch_t *b)
+{
+    if (!b) return;
+    if (b->upload_pending) (void)hipEventSynchronize(b->uploaded);
+    batch_free(b);
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ streaming integration
+
+struct xcorr_stream {
+    Plan plan;  // one chunk
+    int device = 0;
+    hipStream_t copy_stream = nullptr;
+    void *dbuf[2] = {nullptr, nullptr};
+    hipEvent_t copied[2] = {nullptr, nullptr};
+    hipEvent_t consumed[2] = {nullptr, nullptr};
+    hipEvent_t began = nullptr;
+    bool consumed_valid[2] = {false, false};
+    void *out = nullptr;
+    int64_t npush = 0;
+};
+
+namespace {
+
+void stream_free(xcorr_stream *s)
+{
+    if (!s) return;
+    if (s->copy_stream) (void)hipStreamSynchronize(s->copy_stream);
+    for (int k = 0; k < 2; ++k) {
+        if (s->dbuf[k]) (void)hipFree(s->dbuf[k]);
+        if (s->copied[k]) (void)hipEventDestroy(s->copied[k]);
+        if (s->consumed[k]) (void)hipEventDestroy(s->consumed[k]);
+    }
+    if (s->began) (void)hipEventDestroy(s->began);
+    if (s->copy_stream) (void)hipStreamDestroy(s->copy_stream);
+    delete s;
+}
+
+// Wide totals: the output type of a multi-window run.
+int wide_type(int acc) { return acc == ACC_I8 ? OUT_CI64 : OUT_C128; }
+
+}  // namespace
+
+extern "C" {
+
+xcorr_stream_t *xcorr_stream_create(int nstation, int npol, int nchan, int chunk_ntime, xcorr_in_dtype in_dtype,
+                                    xcorr_acc_dtype acc_dtype)
+{
+    if (chunk_ntime < 1) {
+        fail(XCORR_ERR_INVALID_ARG, "chunk_ntime must be >= 1");
+        return nullptr;
+    }
+    xcorr_stream *s = new (std::nothrow) xcorr_stream;
+    if (!s) {
+        fail(XCORR_ERR_OOM, "host allocation");
+        return nullptr;
+    }
+    std::string err;
+    const bool f8ci8 = acc_dtype == XCORR_ACC_F8E4M3_MMA_F32 && in_dtype == XCORR_IN_CI8;
+    int rc = make_plan(nstation, npol, nchan, chunk_ntime, (int)in_dtype, (int)acc_dtype, f8ci8 ? 16 : 0, 0,
+                       &s->plan, &err);
+    if (rc) {
+        fail(rc, err);
+        delete s;
+        return nullptr;
+    }
+    if (f8ci8) s->plan.max_abs = 128;
+    hipError_t e;
+    if ((e = hipGetDevice(&s->device)) != hipSuccess ||
+        (e = hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&s->began, hipEventDisableTiming)) != hipSuccess) {
+        hip_fail((int)e, "stream setup");
+        stream_free(s);
+        return nullptr;
+    }
+    for (int k = 0; k < 2; ++k) {
+        if ((e = hipMalloc(&s->dbuf[k], std::max<size_t>(s->plan.in_bytes, 16))) != hipSuccess ||
+            (e = hipEventCreateWithFlags(&s->copied[k], hipEventDisableTiming)) != hipSuccess ||
+            (e = hipEventCreateWithFlags(&s->consumed[k], hipEventDisableTiming)) != hipSuccess) {
+            hip_fail((int)e, "stream buffers");
+            stream_free(s);
+            return nullptr;
+        }
+    }
+    return s;
+}
+
+int xcorr_stream_set_max_abs(xcorr_stream_t *s, int max_abs)
+{
+    if (!s) return fail(XCORR_ERR_INVALID_ARG, "null stream object");
+    if (s->out) return fail(XCORR_ERR_INVALID_ARG, "an integration is in progress");
+    if (s->plan.in_fmt == IN_CF32) return fail(XCORR_ERR_INVALID_ARG, "max_abs applies to integer samples");
+    Plan p;
+    std::string err;
+    const Plan &o = s->plan;
+    const int rc = make_plan(o.nstation, o.npol, o.nchan, o.ntime, o.in_fmt, o.acc, max_abs, o.tile, &p, &err);
+    if (rc) return fail(rc, err);
+    s->plan = p;
+    return XCORR_OK;
+}
+
+int xcorr_stream_begin(xcorr_stream_t *s, void *out, hipStream_t stream)
+{
+    if (!s || !out) return fail(XCORR_ERR_INVALID_ARG, "null stream object or output");
+    if (s->plan.acc == ACC_F8 && s->plan.max_abs > 16)
+        return fail(XCORR_ERR_UNSUPPORTED, "fp8 e4m3 needs max_abs <= 16 (call xcorr_stream_set_max_abs)");
+    Plan wide = s->plan;
+    wide.out_dtype = wide_type(wide.acc);
+    wide.out_bytes = s->plan.out_bytes / out_value_bytes(s->plan.out_dtype) * out_value_bytes(wide.out_dtype);
+    int rc = launch_zero(out, wide.out_bytes, stream);
+    if (rc) return hip_fail(rc, "zero totals");
+    hipError_t e = hipEventRecord(s->began, stream);
+    if (e != hipSuccess) return hip_fail((int)e, "stream begin event");
+    s->out = out;
+    s->npush = 0;
+    s->consumed_valid[0] = s->consumed_valid[1] = false;
+    return XCORR_OK;
+}
+
+int xcorr_stream_push(xcorr_stream_t *s, const void *host_chunk, hipStream_t stream)
+{
+    if (!s || !host_chunk) return fail(XCORR_ERR_INVALID_ARG, "null stream object or chunk");
+    if (!s->out) return fail(XCORR_ERR_INVALID_ARG, "xcorr_stream_begin was not called");
+    const int slot = (int)(s->npush & 1);
+    hipError_t e;
+    // the copy into this buffer waits for the kernel that last read it (or for the start
+    // of the integration); the kernel waits for the copy
+    e = hipStreamWaitEvent(s->copy_stream, s->consumed_valid[slot] ? s->consumed[slot] : s->began, 0);
+    if (e != hipSuccess) return hip_fail((int)e, "copy wait");
+    if (s->plan.in_bytes) {
+        e = hipMemcpyAsync(s->dbuf[slot], host_chunk, s->plan.in_bytes, hipMemcpyHostToDevice, s->copy_stream);
+        if (e != hipSuccess) return hip_fail((int)e, "chunk copy");
+    }
+    if ((e = hipEventRecord(s->copied[slot], s->copy_stream)) != hipSuccess) return hip_fail((int)e, "copy event");
+    if ((e = hipStreamWaitEvent(stream, s->copied[slot], 0)) != hipSuccess) return hip_fail((int)e, "compute wait");
+    XJob j = job_from_plan(s->plan, s->dbuf[slot], s->out);
+    j.accumulate = 1;  // add into the wide totals
+    const int64_t total = j.grid;
+    for (int64_t b0 = 0; b0 < total; b0 += MAX_BLOCKS_PER_LAUNCH) {
+        j.block0 = b0;
+        j.grid = std::min<int64_t>(MAX_BLOCKS_PER_LAUNCH, total - b0);
+        const int rc = s->plan.acc == ACC_F32_CMAC ? launch_cmac(j, s->plan.in_fmt, stream)
+                                                   : launch_mfma(j, s->plan.acc, s->plan.in_fmt, stream);
+        if (rc) return hip_fail(rc, "kernel launch");
+    }
+    if ((e = hipEventRecord(s->consumed[slot], stream)) != hipSuccess) return hip_fail((int)e, "compute event");
+    s->consumed_valid[slot] = true;
+    s->npush += 1;
+    return XCORR_OK;
+}
+
+int64_t xcorr_stream_end(xcorr_stream_t *s, hipStream_t stream)
+{
+    (void)stream;  // every chunk's kernel already runs on `stream`, after its copy
+    if (!s) return fail(XCORR_ERR_INVALID_ARG, "null stream object");
+    if (!s->out) return fail(XCORR_ERR_INVALID_ARG, "xcorr_stream_begin was not called");
+    s->out = nullptr;
+    return s->npush * (int64_t)s->plan.ntime;
+}
+
+size_t xcorr_stream_chunk_bytes(const xcorr_stream_t *s) { return s ? s->plan.in_bytes : 0; }
+
+size_t xcorr_stream_out_bytes(const xcorr_stream_t *s)
+{
+    if (!s) return 0;
+    return s->plan.out_bytes / out_value_bytes(s->plan.out_dtype) * out_value_bytes(wide_type(s->plan.acc));
+}
+
+int xcorr_stream_out_type(const xcorr_stream_t *s)
+{
+    if (!s) return fail(XCORR_ERR_INVALID_ARG, "null stream object");
+    return wide_type(s->plan.acc);
+}
+
+void xcorr_stream_destroy(xcorr_stream_t *s) { stream_free(s); }
+
+}  // extern "C"

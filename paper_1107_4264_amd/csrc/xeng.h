@@ -47,13 +47,23 @@ int launch_mfma(const XJob &job, int acc, int in_fmt, hipStream_t stream);
 int launch_cmac(const XJob &job, int in_fmt, hipStream_t stream);
 int launch_zero(void *ptr, size_t bytes, hipStream_t stream);
 
-// Batched persistent launch: one grid works through `items` (sorted longest first) of
-// jobs that share the arithmetic path and input format.
-int launch_mfma_batch(const XJob *jobs_dev, const XItem *items_dev, int64_t nitems,
-                      unsigned int *counter_dev, int acc, int in_fmt, int tile, int nblocks,
+// Batched persistent launch.  The work list is split into NQUEUE queues (one per XCD: a
+// channel's items all go to one queue); workgroup b takes items from queue b % NQUEUE
+// through an atomic counter, then steals from the other queues, and exits when all are
+// empty.  counters_dev holds NQUEUE counters spaced COUNTER_STRIDE words apart, zeroed
+// before every launch.
+constexpr int NQUEUE = 8;
+constexpr int COUNTER_STRIDE = 16;
+struct XQueues {
+    int64_t begin[NQUEUE];
+    int64_t end[NQUEUE];
+};
+
+int launch_mfma_batch(const XJob *jobs_dev, const XItem *items_dev, const XQueues &queues,
+                      unsigned int *counters_dev, int acc, int in_fmt, int tile, int load_mode, int nblocks,
                       hipStream_t stream);
-int launch_cmac_batch(const XJob *jobs_dev, const XItem *items_dev, int64_t nitems,
-                      unsigned int *counter_dev, int in_fmt, int nblocks, hipStream_t stream);
+int launch_cmac_batch(const XJob *jobs_dev, const XItem *items_dev, const XQueues &queues,
+                      unsigned int *counters_dev, int in_fmt, int nblocks, hipStream_t stream);
 
 // Number of compute units of the current device (for persistent grids).
 int device_cus();

@@ -195,7 +195,8 @@ struct Tile {
     static constexpr int LDS_BYTES = 2 * 2 * SIDE_BYTES;     // 2 buffers x 2 sides
     static constexpr int FULL = (1 << (NB * NB)) - 1;        // every block of the wave
     static constexpr int DIAG = NB == 2 ? 0xD : 1;           // blocks (0,0), (1,0), (1,1)
-    static constexpr int DEPTH = ACC == ACC_F16 ? 2 : 1;     // register prefetch depth
+    static constexpr int DEPTH = ACC == ACC_F16 ? 3 : (ACC == ACC_I8 ? 2 : 1);  // blocks in flight
+    static constexpr bool INTERLEAVE = false;                // convert between K-steps
     static_assert(2 * NT <= 256, "at most one staging task per thread");
     static_assert(TB % (2 * G) == 0, "time block holds whole K-steps");
 };
@@ -409,13 +410,14 @@ __device__ __forceinline__ void read_frags(const uint8_t *base, int col_side, in
 
 // One staged block: K-steps of 2G samples, the operands of step s+1 read from LDS while
 // the MFMAs of step s run.  With two 32x32 blocks per wave side the wave computes blocks
-// (0,0), (1,0), (1,1) and, unless it sits on the diagonal of a diagonal tile, block (0,1);
-// the condition is wave-uniform, so the accumulators keep one register assignment and only
-// a scalar branch guards the last pair of MFMAs.
-template <int ACC, int IN, int TILE>
-__device__ __forceinline__ void mac_block(const uint8_t *base, int col_side, int wr, int wc, int lane, bool do01,
+// (0,0), (1,0), (1,1) and, with DO01, block (0,1) (not on the diagonal of a diagonal
+// tile).  after(s) runs once the MFMAs of step s are issued: the caller converts a share of
+// the next block there, so that its VALU work issues while the MFMAs execute.
+template <int ACC, int IN, int TILE, bool DO01, typename After>
+__device__ __forceinline__ void mac_block(const uint8_t *base, int col_side, int wr, int wc, int lane,
                                           typename Tile<ACC, IN, TILE>::acc_t (&re)[Tile<ACC, IN, TILE>::NB][Tile<ACC, IN, TILE>::NB],
-                                          typename Tile<ACC, IN, TILE>::acc_t (&im)[Tile<ACC, IN, TILE>::NB][Tile<ACC, IN, TILE>::NB])
+                                          typename Tile<ACC, IN, TILE>::acc_t (&im)[Tile<ACC, IN, TILE>::NB][Tile<ACC, IN, TILE>::NB],
+                                          After &&after)
 {
     using T = Tile<ACC, IN, TILE>;
     constexpr int NB = T::NB;
@@ -423,7 +425,7 @@ __device__ __forceinline__ void mac_block(const uint8_t *base, int col_side, int
     const int r32 = lane & 31, half = lane >> 5;
     Frag<T::WORDS> A[2][NB], B[2][NB];
     read_frags<ACC, IN, TILE>(base, col_side, wr, wc, r32, half, A[0], B[0]);
-    static_for<KSTEPS>([&](auto S) {
+    static_for<KSTEPS>([&](auto S) __attribute__((always_inline)) {
         constexpr int s = decltype(S)::value;
         constexpr int cur = s & 1;
         if constexpr (s + 1 < KSTEPS)
@@ -440,11 +442,12 @@ __device__ __forceinline__ void mac_block(const uint8_t *base, int col_side, int
             mma(im[1][0], A[cur][1], C[0]);
             mma(re[1][1], A[cur][1], B[cur][1]);
             mma(im[1][1], A[cur][1], C[1]);
-            if (do01) {
+            if constexpr (DO01) {
                 mma(re[0][1], A[cur][0], B[cur][1]);
                 mma(im[0][1], A[cur][0], C[1]);
             }
         }
+        after(S);
     });
 }
 
@@ -602,7 +605,7 @@ __device__ __forceinline__ void process_item(const XJob &p, int f, int g, int w,
     const int i0 = (side == 0 ? row0 : col0) + chunk * T::CI;
     const uint32_t row_stride = (uint32_t)((int64_t)p.nchan * p.nin * T::BPC);
     using rows_t = uint32_t[T::G][T::LW];
-    rows_t ra, rb;
+    rows_t rows[T::DEPTH];
 
     // Loads past the last block read nothing (empty descriptor) and are issued anyway, so
     // the loop carries no branches between a load and the use of its registers.
@@ -614,48 +617,52 @@ __device__ __forceinline__ void process_item(const XJob &p, int f, int g, int w,
     const int col_side = diag ? 0 : 1;
     // Any wave with a block to store computes (0,0), (1,0), (1,1), and (0,1) unless the
     // mask is the diagonal pattern; blocks of zero padding are computed but not stored.
+    // The choice is made once per tile: the time loop exists in both forms, so the
+    // accumulators never pass through a branch inside the loop.
     const bool active = mask != 0;
-    const bool do01 = mask != T::DIAG;
+    constexpr int KSTEPS = T::NTG / 2;
+    constexpr int UPS = T::CI / KSTEPS;  // units converted after each K-step
 
-    // Multiply the block in LDS buffer `cur`, then convert `rows` (the next block) into
-    // buffer `cur ^ 1`.  (Converting a share after each K-step instead, so that the VALU
-    // work issues under the MFMAs, needs more registers than two waves per SIMD allow.)
-    auto step = [&](int cur, const rows_t &rows) {
-        if (active)
-            mac_block<ACC, IN, TILE>(lds + cur * 2 * T::SIDE_BYTES, col_side, wr, wc, lane, do01, re, im);
-        stage(rows, cur ^ 1);
+    auto run = [&](auto D) __attribute__((always_inline)) {
+        constexpr bool DO01 = decltype(D)::value;
+        // Multiply the block in LDS buffer `cur` while converting `rows` (the next block)
+        // into buffer `cur ^ 1`, a share after each K-step (INTERLEAVE) or all at the end.
+        auto step = [&](int cur, const rows_t &rows) __attribute__((always_inline)) {
+            auto after = [&](auto S) __attribute__((always_inline)) {
+                constexpr int s = decltype(S)::value;
+                if constexpr (T::INTERLEAVE)
+                    stage_store<ACC, IN, TILE, s * UPS, (s + 1) * UPS>(lds, cur ^ 1, side, tg, chunk, rows);
+            };
+            if (active)
+                mac_block<ACC, IN, TILE, DO01>(lds + cur * 2 * T::SIDE_BYTES, col_side, wr, wc, lane, re, im, after);
+            else if constexpr (T::INTERLEAVE)
+                static_for<KSTEPS>(after);
+            if constexpr (!T::INTERLEAVE) stage(rows, cur ^ 1);
+        };
+        // DEPTH register slots: while block b is multiplied, blocks b+1 .. b+DEPTH-1 are
+        // in flight (block k lives in slot k % DEPTH); block b+1 is converted into the
+        // other LDS buffer at the end of the step and block b+DEPTH is loaded into the
+        // slot block b left.  One barrier per block.
+        static_for<T::DEPTH>([&](auto S) __attribute__((always_inline)) { load(rows[decltype(S)::value], decltype(S)::value); });
+        stage(rows[0], 0);
+        __syncthreads();
+        for (int blk = 0; blk < nblk; blk += T::DEPTH) {
+            bool done = false;
+            static_for<T::DEPTH>([&](auto S) __attribute__((always_inline)) {
+                constexpr int k = decltype(S)::value;
+                const int b = blk + k;
+                if (done || b >= nblk) {
+                    done = true;
+                    return;
+                }
+                load(rows[k], b + T::DEPTH);
+                step(b & 1, rows[(k + 1) % T::DEPTH]);
+                __syncthreads();
+            });
+        }
     };
-
-    if constexpr (T::DEPTH == 2) {
-        // Two register slots: block b+2 is loaded while block b is multiplied and block
-        // b+1 (loaded one step earlier) is converted into the other LDS buffer.
-        load(ra, 0);
-        load(rb, 1);
-        stage(ra, 0);
-        __syncthreads();
-        for (int blk = 0; blk < nblk; blk += 2) {
-            load(ra, blk + 2);
-            step(0, rb);
-            __syncthreads();
-            if (blk + 1 >= nblk) break;
-            load(rb, blk + 3);
-            step(1, ra);
-            __syncthreads();
-        }
-    } else {
-        // One register slot: block b+1 is loaded while block b is multiplied; it is
-        // converted after the last K-step.
-        load(ra, 0);
-        stage(ra, 0);
-        __syncthreads();
-        for (int blk = 0; blk < nblk; ++blk) {
-            load(ra, blk + 1);
-            const int cur = blk & 1;
-            if (active) mac_block<ACC, IN, TILE>(lds + cur * 2 * T::SIDE_BYTES, col_side, wr, wc, lane, do01, re, im);
-            stage(ra, cur ^ 1);
-            __syncthreads();
-        }
-    }
+    if (mask != T::DIAG) run(std::true_type{});
+    else run(std::false_type{});
 
     store_tile<ACC, IN, TILE>(p, f, row0, col0, wr, wc, lane, mask, re, im);
 }
@@ -693,25 +700,26 @@ __global__ __launch_bounds__(NTHREADS, 2) void xeng_mfma_kernel(XJob p)
     process_item<ACC, IN, TILE, MODE>(p, f, g, w, lds);
 }
 
-// Persistent batched kernel: workgroups take (job, channel, tile, window) items off a
-// global counter until the list is exhausted; every workgroup reaches the exit.
-template <int ACC, int IN, int TILE>
+// Persistent batched kernel: workgroups take (job, channel, tile, window) items off the
+// queues until all are empty (see XQueues); every workgroup reaches the exit.
+template <int ACC, int IN, int TILE, int MODE>
 __global__ __launch_bounds__(NTHREADS, 2) void xeng_mfma_batch_kernel(const XJob *jobs, const XItem *items,
-                                                                      int64_t nitems, unsigned int *counter)
+                                                                      XQueues q, unsigned int *counters)
 {
     uint8_t *lds = dyn_lds;
     __shared__ int64_t next;
-    for (;;) {
-        if (threadIdx.x == 0) next = (int64_t)atomicAdd(counter, 1u);
-        __syncthreads();
-        const int64_t it = next;
-        __syncthreads();
-        if (it >= nitems) break;
-        const XItem item = items[it];
-        const XJob p = jobs[item.job];
-        if (p.load_mode == LOAD_VEC) process_item<ACC, IN, TILE, LOAD_VEC>(p, item.chan, item.tile, item.window, lds);
-        else if (p.load_mode == LOAD_WORD) process_item<ACC, IN, TILE, LOAD_WORD>(p, item.chan, item.tile, item.window, lds);
-        else process_item<ACC, IN, TILE, LOAD_ELEM>(p, item.chan, item.tile, item.window, lds);
+    const int q0 = blockIdx.x % NQUEUE;
+    for (int qi = 0; qi < NQUEUE; ++qi) {
+        const int qq = (q0 + qi) % NQUEUE;
+        for (;;) {
+            if (threadIdx.x == 0) next = q.begin[qq] + (int64_t)atomicAdd(&counters[qq * COUNTER_STRIDE], 1u);
+            __syncthreads();
+            const int64_t it = next;
+            __syncthreads();
+            if (it >= q.end[qq]) break;
+            const XItem item = items[it];
+            process_item<ACC, IN, TILE, MODE>(jobs[item.job], item.chan, item.tile, item.window, lds);
+        }
     }
 }
 
@@ -746,14 +754,14 @@ int launch_one(const XJob &job, hipStream_t stream)
     return launch_mode<ACC, IN, TILE, LOAD_ELEM>(job, stream);
 }
 
-template <int ACC, int IN, int TILE>
-int launch_batch(const XJob *jobs, const XItem *items, int64_t nitems, unsigned int *counter,
-                 int nblocks, hipStream_t stream)
+template <int ACC, int IN, int TILE, int MODE>
+int launch_batch(const XJob *jobs, const XItem *items, const XQueues &q, unsigned int *counters, int nblocks,
+                 hipStream_t stream)
 {
     constexpr int LDS = Tile<ACC, IN, TILE>::LDS_BYTES;
-    auto k = xeng_mfma_batch_kernel<ACC, IN, TILE>;
+    auto k = xeng_mfma_batch_kernel<ACC, IN, TILE, MODE>;
     if (int e = allow_lds(k, LDS)) return e;
-    hipLaunchKernelGGL(k, dim3(nblocks), dim3(NTHREADS), LDS, stream, jobs, items, nitems, counter);
+    hipLaunchKernelGGL(k, dim3(nblocks), dim3(NTHREADS), LDS, stream, jobs, items, q, counters);
     return (int)hipGetLastError();
 }
 
@@ -773,21 +781,30 @@ int launch_in(const XJob &job, int in_fmt, hipStream_t stream)
     return (int)hipErrorInvalidValue;
 }
 
-template <int ACC, int IN>
-int launch_batch_tile(const XJob *jobs, const XItem *items, int64_t n, unsigned int *counter,
-                      int tile, int nblocks, hipStream_t stream)
+template <int ACC, int IN, int TILE>
+int launch_batch_mode(const XJob *jobs, const XItem *items, const XQueues &q, unsigned int *counters, int mode,
+                      int nblocks, hipStream_t stream)
 {
-    if (tile == 128) return launch_batch<ACC, IN, 128>(jobs, items, n, counter, nblocks, stream);
-    if (tile == 64) return launch_batch<ACC, IN, 64>(jobs, items, n, counter, nblocks, stream);
+    if (mode == LOAD_VEC) return launch_batch<ACC, IN, TILE, LOAD_VEC>(jobs, items, q, counters, nblocks, stream);
+    if (mode == LOAD_WORD) return launch_batch<ACC, IN, TILE, LOAD_WORD>(jobs, items, q, counters, nblocks, stream);
+    return launch_batch<ACC, IN, TILE, LOAD_ELEM>(jobs, items, q, counters, nblocks, stream);
+}
+
+template <int ACC, int IN>
+int launch_batch_tile(const XJob *jobs, const XItem *items, const XQueues &q, unsigned int *counters, int tile,
+                      int mode, int nblocks, hipStream_t stream)
+{
+    if (tile == 128) return launch_batch_mode<ACC, IN, 128>(jobs, items, q, counters, mode, nblocks, stream);
+    if (tile == 64) return launch_batch_mode<ACC, IN, 64>(jobs, items, q, counters, mode, nblocks, stream);
     return (int)hipErrorInvalidValue;
 }
 
 template <int ACC>
-int launch_batch_in(const XJob *jobs, const XItem *items, int64_t n, unsigned int *counter, int in_fmt,
-                    int tile, int nblocks, hipStream_t stream)
+int launch_batch_in(const XJob *jobs, const XItem *items, const XQueues &q, unsigned int *counters, int in_fmt,
+                    int tile, int mode, int nblocks, hipStream_t stream)
 {
-    if (in_fmt == IN_CI8) return launch_batch_tile<ACC, IN_CI8>(jobs, items, n, counter, tile, nblocks, stream);
-    if (in_fmt == IN_CI4) return launch_batch_tile<ACC, IN_CI4>(jobs, items, n, counter, tile, nblocks, stream);
+    if (in_fmt == IN_CI8) return launch_batch_tile<ACC, IN_CI8>(jobs, items, q, counters, tile, mode, nblocks, stream);
+    if (in_fmt == IN_CI4) return launch_batch_tile<ACC, IN_CI4>(jobs, items, q, counters, tile, mode, nblocks, stream);
     return (int)hipErrorInvalidValue;
 }
 
@@ -804,15 +821,15 @@ int launch_mfma(const XJob &job, int acc, int in_fmt, hipStream_t stream)
     }
 }
 
-int launch_mfma_batch(const XJob *jobs_dev, const XItem *items_dev, int64_t nitems,
-                      unsigned int *counter_dev, int acc, int in_fmt, int tile, int nblocks,
+int launch_mfma_batch(const XJob *jobs_dev, const XItem *items_dev, const XQueues &queues,
+                      unsigned int *counters_dev, int acc, int in_fmt, int tile, int load_mode, int nblocks,
                       hipStream_t stream)
 {
-    if (nitems <= 0) return 0;
+    if (nblocks <= 0) return 0;
     switch (acc) {
-    case ACC_I8: return launch_batch_in<ACC_I8>(jobs_dev, items_dev, nitems, counter_dev, in_fmt, tile, nblocks, stream);
-    case ACC_F16: return launch_batch_in<ACC_F16>(jobs_dev, items_dev, nitems, counter_dev, in_fmt, tile, nblocks, stream);
-    case ACC_F8: return launch_batch_in<ACC_F8>(jobs_dev, items_dev, nitems, counter_dev, in_fmt, tile, nblocks, stream);
+    case ACC_I8: return launch_batch_in<ACC_I8>(jobs_dev, items_dev, queues, counters_dev, in_fmt, tile, load_mode, nblocks, stream);
+    case ACC_F16: return launch_batch_in<ACC_F16>(jobs_dev, items_dev, queues, counters_dev, in_fmt, tile, load_mode, nblocks, stream);
+    case ACC_F8: return launch_batch_in<ACC_F8>(jobs_dev, items_dev, queues, counters_dev, in_fmt, tile, load_mode, nblocks, stream);
     default: return (int)hipErrorInvalidValue;
     }
 }

@@ -34,6 +34,11 @@ class XcorrError(RuntimeError):
         self.code = code
 
 
+class Job(ctypes.Structure):
+    _fields_ = [("nstation", ctypes.c_int), ("npol", ctypes.c_int), ("nchan", ctypes.c_int),
+                ("ntime", ctypes.c_int)]
+
+
 class PlanInfo(ctypes.Structure):
     _fields_ = [
         ("nin", ctypes.c_int), ("tile", ctypes.c_int), ("ntile_side", ctypes.c_int),
@@ -69,6 +74,23 @@ def _load():
         "xcorr_plan": (c_int, [c_int, c_int, c_int, c_int, c_int, c_int, c_int, ctypes.POINTER(PlanInfo)]),
         "xcorr_window_limit": (c_i64, [c_int, c_int, c_int]),
         "xcorr_tile_coords": (c_int, [c_i64, ctypes.POINTER(c_i64), ctypes.POINTER(c_i64)]),
+        "xcorr_batch_create": (c_vp, [c_int, c_vp, c_int, c_int]),
+        "xcorr_batch_set_max_abs": (c_int, [c_vp, c_int]),
+        "xcorr_batch_run": (c_int, [c_vp, c_vp, c_vp, c_vp]),
+        "xcorr_batch_in_bytes": (c_sz, [c_vp, c_int]),
+        "xcorr_batch_out_bytes": (c_sz, [c_vp, c_int]),
+        "xcorr_batch_out_type": (c_int, [c_vp, c_int]),
+        "xcorr_batch_items": (c_i64, [c_vp]),
+        "xcorr_batch_destroy": (None, [c_vp]),
+        "xcorr_stream_create": (c_vp, [c_int, c_int, c_int, c_int, c_int, c_int]),
+        "xcorr_stream_set_max_abs": (c_int, [c_vp, c_int]),
+        "xcorr_stream_begin": (c_int, [c_vp, c_vp, c_vp]),
+        "xcorr_stream_push": (c_int, [c_vp, c_vp, c_vp]),
+        "xcorr_stream_end": (c_i64, [c_vp, c_vp]),
+        "xcorr_stream_chunk_bytes": (c_sz, [c_vp]),
+        "xcorr_stream_out_bytes": (c_sz, [c_vp]),
+        "xcorr_stream_out_type": (c_int, [c_vp]),
+        "xcorr_stream_destroy": (None, [c_vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -150,6 +172,90 @@ def xcorr_tile_coords(g):
     return bx.value, by.value
 
 
+def xcorr_batch_create(jobs, in_dtype, acc_dtype):
+    """jobs: sequence of dicts or tuples (nstation, npol, nchan, ntime)."""
+    arr = (Job * len(jobs))()
+    for k, j in enumerate(jobs):
+        if isinstance(j, dict):
+            j = (j["nstation"], j["npol"], j["nchan"], j["ntime"])
+        arr[k] = Job(*j)
+    b = _lib.xcorr_batch_create(len(jobs), ctypes.cast(arr, ctypes.c_void_p), in_dtype, acc_dtype)
+    if not b:
+        raise XcorrError(-1, last_error())
+    return b
+
+
+def xcorr_batch_set_max_abs(b, max_abs):
+    return _check(_lib.xcorr_batch_set_max_abs(b, max_abs))
+
+
+def xcorr_batch_run(b, in_ptrs, out_ptrs, stream_ptr):
+    n = len(in_ptrs)
+    ins = (ctypes.c_void_p * n)(*in_ptrs)
+    outs = (ctypes.c_void_p * n)(*out_ptrs)
+    return _check(_lib.xcorr_batch_run(b, ctypes.cast(ins, ctypes.c_void_p), ctypes.cast(outs, ctypes.c_void_p),
+                                       stream_ptr))
+
+
+def xcorr_batch_in_bytes(b, job):
+    return int(_lib.xcorr_batch_in_bytes(b, job))
+
+
+def xcorr_batch_out_bytes(b, job):
+    return int(_lib.xcorr_batch_out_bytes(b, job))
+
+
+def xcorr_batch_out_type(b, job):
+    return _check(_lib.xcorr_batch_out_type(b, job))
+
+
+def xcorr_batch_items(b):
+    return int(_lib.xcorr_batch_items(b))
+
+
+def xcorr_batch_destroy(b):
+    _lib.xcorr_batch_destroy(b)
+
+
+def xcorr_stream_create(nstation, npol, nchan, chunk_ntime, in_dtype, acc_dtype):
+    s = _lib.xcorr_stream_create(nstation, npol, nchan, chunk_ntime, in_dtype, acc_dtype)
+    if not s:
+        raise XcorrError(-1, last_error())
+    return s
+
+
+def xcorr_stream_set_max_abs(s, max_abs):
+    return _check(_lib.xcorr_stream_set_max_abs(s, max_abs))
+
+
+def xcorr_stream_begin(s, out_ptr, stream_ptr):
+    return _check(_lib.xcorr_stream_begin(s, out_ptr, stream_ptr))
+
+
+def xcorr_stream_push(s, host_ptr, stream_ptr):
+    return _check(_lib.xcorr_stream_push(s, host_ptr, stream_ptr))
+
+
+def xcorr_stream_end(s, stream_ptr):
+    return _check(_lib.xcorr_stream_end(s, stream_ptr))
+
+
+def xcorr_stream_chunk_bytes(s):
+    return int(_lib.xcorr_stream_chunk_bytes(s))
+
+
+def xcorr_stream_out_bytes(s):
+    return int(_lib.xcorr_stream_out_bytes(s))
+
+
+def xcorr_stream_out_type(s):
+    return _check(_lib.xcorr_stream_out_type(s))
+
+
+def xcorr_stream_destroy(s):
+    _lib.xcorr_stream_destroy(s)
+
+
 # ------------------------------------------------------------------ torch convenience
 
 def out_torch_dtype(out_type):
@@ -217,3 +323,100 @@ class Correlator:
             raise ValueError("output buffer does not match the plan")
         xcorr_run(self.h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream))
         return out
+
+
+class Batch:
+    """Many jobs in one persistent launch (torch tensors for memory)."""
+
+    def __init__(self, jobs, in_dtype="ci8", acc="i8", max_abs=None):
+        self.jobs = [j if isinstance(j, dict) else dict(zip(("nstation", "npol", "nchan", "ntime"), j))
+                     for j in jobs]
+        self.in_dtype = IN_NAMES.get(in_dtype, in_dtype)
+        self.acc = ACC_NAMES.get(acc, acc)
+        self.b = xcorr_batch_create(self.jobs, self.in_dtype, self.acc)
+        if max_abs is not None:
+            xcorr_batch_set_max_abs(self.b, int(max_abs))
+
+    def close(self):
+        if self.b:
+            xcorr_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def out_shape(self, k):
+        j = self.jobs[k]
+        nbl = j["nstation"] * (j["nstation"] + 1) // 2
+        return (j["nchan"], nbl, j["npol"] * j["npol"], 2)
+
+    def empty_outs(self, device="cuda"):
+        import torch
+
+        return [torch.empty(self.out_shape(k), dtype=out_torch_dtype(xcorr_batch_out_type(self.b, k)), device=device)
+                for k in range(len(self.jobs))]
+
+    def run(self, xs, outs=None, stream=None):
+        if len(xs) != len(self.jobs):
+            raise ValueError("one input per job")
+        for k, x in enumerate(xs):
+            if x.numel() * x.element_size() != xcorr_batch_in_bytes(self.b, k):
+                raise ValueError(f"input {k} size does not match the plan")
+        if outs is None:
+            outs = self.empty_outs(xs[0].device)
+        for k, o in enumerate(outs):
+            if o.numel() * o.element_size() != xcorr_batch_out_bytes(self.b, k):
+                raise ValueError(f"output {k} size does not match the plan")
+        xcorr_batch_run(self.b, [x.data_ptr() for x in xs], [o.data_ptr() for o in outs], _stream_ptr(stream))
+        return outs
+
+
+class Stream:
+    """Chunked integration with copy/compute overlap (Algorithm 1).  Chunks are host tensors
+    (pinned for asynchronous copies); totals are a device tensor of the wide type."""
+
+    def __init__(self, nstation, npol, nchan, chunk_ntime, in_dtype="ci8", acc="i8", max_abs=None):
+        self.nstation, self.npol, self.nchan, self.chunk_ntime = nstation, npol, nchan, chunk_ntime
+        self.s = xcorr_stream_create(nstation, npol, nchan, chunk_ntime, IN_NAMES.get(in_dtype, in_dtype),
+                                     ACC_NAMES.get(acc, acc))
+        if max_abs is not None:
+            xcorr_stream_set_max_abs(self.s, int(max_abs))
+        self.out = None
+
+    def close(self):
+        if self.s:
+            xcorr_stream_destroy(self.s)
+            self.s = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def empty_out(self, device="cuda"):
+        import torch
+
+        nbl = self.nstation * (self.nstation + 1) // 2
+        return torch.empty((self.nchan, nbl, self.npol * self.npol, 2),
+                           dtype=out_torch_dtype(xcorr_stream_out_type(self.s)), device=device)
+
+    def begin(self, out=None, stream=None):
+        self.out = self.empty_out() if out is None else out
+        if self.out.numel() * self.out.element_size() != xcorr_stream_out_bytes(self.s):
+            raise ValueError("totals buffer does not match the plan")
+        xcorr_stream_begin(self.s, ctypes.c_void_p(self.out.data_ptr()), _stream_ptr(stream))
+        return self.out
+
+    def push(self, chunk, stream=None):
+        if chunk.is_cuda:
+            raise ValueError("chunks come from host memory")
+        if chunk.numel() * chunk.element_size() != xcorr_stream_chunk_bytes(self.s):
+            raise ValueError("chunk size does not match the plan")
+        xcorr_stream_push(self.s, ctypes.c_void_p(chunk.data_ptr()), _stream_ptr(stream))
+
+    def end(self, stream=None):
+        return xcorr_stream_end(self.s, _stream_ptr(stream))
