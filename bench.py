@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
     ap.add_argument("--only", default=None, help="time only this path (for profiling runs)")
+    ap.add_argument("--tile", type=int, default=0,
+                    help="kernel shape for the matrix-core paths: 0 automatic, 64/128 tiles, 256 whole channel")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one device copy of 1 GiB (reference for HBM byte counters)")
     return ap.parse_args()
@@ -78,8 +80,9 @@ def main():
     outs = {}
     stream = torch.cuda.current_stream()
     for p in paths:
-        c = X.Correlator(ns, npol, F, T, "ci8", p, max_abs=max_abs)
-        plan = X.xcorr_plan(ns, npol, F, T, X.IN_CI8, X.ACC_NAMES[p], max_abs)
+        tile = args.tile if p != "f32" else 0
+        c = X.Correlator(ns, npol, F, T, "ci8", p, max_abs=max_abs, tile=tile)
+        plan = X.xcorr_plan(ns, npol, F, T, X.IN_CI8, X.ACC_NAMES[p], max_abs, tile)
         out = c.empty_out(dev)
         for _ in range(args.warmup):
             c.run(x, out)
@@ -104,6 +107,7 @@ def main():
             "algorithmic_gbps": alg_bytes / (ms * 1e-3) / 1e9,
             "out_type": ["ci32", "ci64", "c64", "c128"][plan["out_dtype"]],
             "windows": plan["nwindows"],
+            "tile": plan["tile"],
             "launches_per_step": 1 if plan["nwindows"] == 1 else 2,
         }
         outs[p] = out
@@ -128,7 +132,7 @@ def main():
 
     head = "f16" if "f16" in results else paths[0]
     hr = results[head]
-    plan = X.xcorr_plan(ns, npol, F, T, X.IN_CI8, X.ACC_NAMES[head], max_abs)
+    plan = X.xcorr_plan(ns, npol, F, T, X.IN_CI8, X.ACC_NAMES[head], max_abs, args.tile if head != "f32" else 0)
     line = {
         "metric": METRIC,
         "value": round(hr["tflops"], 3),

@@ -116,6 +116,21 @@ xcorr_handle_t *xcorr_create(int nstation, int npol, int nchan, int ntime,
  * CI8, 1..8 for CI4).  Re-plans the accumulation windows and may change the output type. */
 int xcorr_set_max_abs(xcorr_handle_t *h, int max_abs);
 
+/* Choose the kernel shape (Sec. 4.2's tiling of the triangle, re-planned for gfx950):
+ *   0    automatic (the default): 256 when allowed and nin > 192, else 128 (64 when
+ *        nin <= 64; always 64 for F32_CMAC);
+ *   64, 128  square tiles of that many inputs, one workgroup per (channel, tile, window);
+ *   256  whole channel: one persistent workgroup per compute unit holds the triangle of a
+ *        channel and reads every sample once; needs CI8 input, the int8 or fp16 path and
+ *        nin <= 256, a multiple of 8.  An input pointer that is not 16-byte aligned runs
+ *        128-tiles instead.
+ * All shapes give bit-identical visibilities.  XCORR_ERR_INVALID_ARG for a shape the job
+ * does not allow (the handle keeps its previous shape). */
+int xcorr_set_tile(xcorr_handle_t *h, int tile);
+
+/* The kernel shape the handle runs (64, 128 or 256), or an error code. */
+int xcorr_get_tile(const xcorr_handle_t *h);
+
 /* Compute the visibilities of `in` (device, xcorr_in_bytes) into `out` (device,
  * xcorr_out_bytes) on `stream` (0 = the null stream). */
 int xcorr_run(xcorr_handle_t *h, const void *in, void *out, hipStream_t stream);
@@ -218,7 +233,7 @@ void xcorr_stream_destroy(xcorr_stream_t *s);
  */
 typedef struct {
     int nin;             /* nstation * npol */
-    int tile;            /* inputs per side of a square tile of the triangle */
+    int tile;            /* inputs per side of a square tile; 256: whole channel */
     int ntile_side;      /* ceil(nin / tile) */
     int tiles_per_chan;  /* ntile_side * (ntile_side + 1) / 2 */
     int window;          /* samples per accumulation window */
@@ -232,8 +247,10 @@ typedef struct {
     size_t out_bytes;
 } xcorr_plan_info;
 
+/* Plan a job as xcorr_create + xcorr_set_max_abs (max_abs 0: the default) +
+ * xcorr_set_tile (tile 0: automatic) would. */
 int xcorr_plan(int nstation, int npol, int nchan, int ntime, xcorr_in_dtype in_dtype,
-               xcorr_acc_dtype acc_dtype, int max_abs, xcorr_plan_info *info);
+               xcorr_acc_dtype acc_dtype, int max_abs, int tile, xcorr_plan_info *info);
 
 /* Largest window (samples) for which the accumulators of acc_dtype stay exact with
  * components bounded by max_abs; < 0 on a bad argument. */

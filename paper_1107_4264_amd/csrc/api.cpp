@@ -72,6 +72,37 @@ XJob job_from_plan(const Plan &pl, const void *in, void *out)
     return j;
 }
 
+// Launch the kernels of one job on `stream` (the output already prepared): the persistent
+// whole-channel kernel with one workgroup per compute unit, or one tile kernel launch per
+// 2^24 blocks.
+int launch_job(const Plan &pl, XJob j, hipStream_t stream)
+{
+    if (pl.tile == CHAN_TILE) {
+        if ((uintptr_t)j.in % 16 == 0) {
+            const int cus = device_cus();
+            if (cus <= 0) return (int)hipErrorNoDevice;
+            j.grid = std::min<int64_t>(pl.nitems, cus);
+            return launch_chan(j, pl.acc, stream);
+        }
+        // the row copies need 16-byte aligned rows: run 128-tiles instead
+        Plan tp;
+        std::string err;
+        if (make_plan(pl.nstation, pl.npol, pl.nchan, pl.ntime, pl.in_fmt, pl.acc, pl.max_abs, 128, &tp, &err))
+            return (int)hipErrorInvalidValue;
+        XJob tj = job_from_plan(tp, j.in, j.out);
+        tj.accumulate = j.accumulate;
+        return launch_job(tp, tj, stream);
+    }
+    const int64_t total = j.grid;
+    for (int64_t b0 = 0; b0 < total; b0 += MAX_BLOCKS_PER_LAUNCH) {
+        j.block0 = b0;
+        j.grid = std::min<int64_t>(MAX_BLOCKS_PER_LAUNCH, total - b0);
+        const int e = pl.acc == ACC_F32_CMAC ? launch_cmac(j, pl.in_fmt, stream) : launch_mfma(j, pl.acc, pl.in_fmt, stream);
+        if (e) return e;
+    }
+    return 0;
+}
+
 // Enqueue one job: zero the output when windows are summed into it, then the tile kernels.
 int enqueue_job(const Plan &pl, const void *in, void *out, hipStream_t stream)
 {
@@ -88,14 +119,8 @@ int enqueue_job(const Plan &pl, const void *in, void *out, hipStream_t stream)
         e = launch_zero(out, pl.out_bytes, stream);
         if (e) return hip_fail(e, "zero fill");
     }
-    const int64_t total = j.grid;
-    for (int64_t b0 = 0; b0 < total; b0 += MAX_BLOCKS_PER_LAUNCH) {
-        j.block0 = b0;
-        j.grid = std::min<int64_t>(MAX_BLOCKS_PER_LAUNCH, total - b0);
-        e = pl.acc == ACC_F32_CMAC ? launch_cmac(j, pl.in_fmt, stream)
-                                   : launch_mfma(j, pl.acc, pl.in_fmt, stream);
-        if (e) return hip_fail(e, "kernel launch");
-    }
+    e = launch_job(pl, j, stream);
+    if (e) return hip_fail(e, "kernel launch");
     return XCORR_OK;
 }
 
@@ -143,12 +168,12 @@ static int plan_info_fill(const Plan &p, xcorr_plan_info *info)
 }
 
 int xcorr_plan(int nstation, int npol, int nchan, int ntime, xcorr_in_dtype in_dtype,
-               xcorr_acc_dtype acc_dtype, int max_abs, xcorr_plan_info *info)
+               xcorr_acc_dtype acc_dtype, int max_abs, int tile, xcorr_plan_info *info)
 {
     if (!info) return fail(XCORR_ERR_INVALID_ARG, "null info");
     Plan p;
     std::string err;
-    const int rc = make_plan(nstation, npol, nchan, ntime, (int)in_dtype, (int)acc_dtype, max_abs, 0, &p, &err);
+    const int rc = make_plan(nstation, npol, nchan, ntime, (int)in_dtype, (int)acc_dtype, max_abs, tile, &p, &err);
     if (rc) return fail(rc, err);
     return plan_info_fill(p, info);
 }
@@ -195,6 +220,24 @@ int xcorr_set_max_abs(xcorr_handle_t *h, int max_abs)
     if (rc) return fail(rc, err);
     h->plan = p;
     return XCORR_OK;
+}
+
+int xcorr_set_tile(xcorr_handle_t *h, int tile)
+{
+    if (!h) return fail(XCORR_ERR_INVALID_ARG, "null handle");
+    Plan p;
+    std::string err;
+    const Plan &o = h->plan;
+    const int rc = make_plan(o.nstation, o.npol, o.nchan, o.ntime, o.in_fmt, o.acc, o.max_abs, tile, &p, &err);
+    if (rc) return fail(rc, err);
+    h->plan = p;
+    return XCORR_OK;
+}
+
+int xcorr_get_tile(const xcorr_handle_t *h)
+{
+    if (!h) return fail(XCORR_ERR_INVALID_ARG, "null handle");
+    return h->plan.tile;
 }
 
 int xcorr_run(xcorr_handle_t *h, const void *in, void *out, hipStream_t stream)
@@ -501,6 +544,12 @@ xcorr_stream_t *xcorr_stream_create(int nstation, int npol, int nchan, int chunk
         return nullptr;
     }
     if (f8ci8) s->plan.max_abs = 128;
+    if (s->plan.acc != ACC_F32_CMAC &&
+        64.0 * (double)nchan * s->plan.nin * (double)in_sample_bytes(s->plan.in_fmt) >= 4294901760.0) {
+        fail(XCORR_ERR_RANGE, "nchan * nin too large: 64 samples of all channels must span < 4 GiB");
+        delete s;
+        return nullptr;
+    }
     hipError_t e;
     if ((e = hipGetDevice(&s->device)) != hipSuccess ||
         (e = hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking)) != hipSuccess ||
@@ -571,14 +620,8 @@ int xcorr_stream_push(xcorr_stream_t *s, const void *host_chunk, hipStream_t str
     if ((e = hipStreamWaitEvent(stream, s->copied[slot], 0)) != hipSuccess) return hip_fail((int)e, "compute wait");
     XJob j = job_from_plan(s->plan, s->dbuf[slot], s->out);
     j.accumulate = 1;  // add into the wide totals
-    const int64_t total = j.grid;
-    for (int64_t b0 = 0; b0 < total; b0 += MAX_BLOCKS_PER_LAUNCH) {
-        j.block0 = b0;
-        j.grid = std::min<int64_t>(MAX_BLOCKS_PER_LAUNCH, total - b0);
-        const int rc = s->plan.acc == ACC_F32_CMAC ? launch_cmac(j, s->plan.in_fmt, stream)
-                                                   : launch_mfma(j, s->plan.acc, s->plan.in_fmt, stream);
-        if (rc) return hip_fail(rc, "kernel launch");
-    }
+    const int rc = launch_job(s->plan, j, stream);
+    if (rc) return hip_fail(rc, "kernel launch");
     if ((e = hipEventRecord(s->consumed[slot], stream)) != hipSuccess) return hip_fail((int)e, "compute event");
     s->consumed_valid[slot] = true;
     s->npush += 1;

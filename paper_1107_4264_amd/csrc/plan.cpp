@@ -70,8 +70,15 @@ void tile_coords(int64_t g, int64_t *bx, int64_t *by)
     *bx = g - b * (b + 1) / 2;
 }
 
+bool chan_kernel_ok(int nin, int in_fmt, int acc)
+{
+    return in_fmt == IN_CI8 && (acc == ACC_I8 || acc == ACC_F16) && nin % 8 == 0 && nin >= 1 && nin <= CHAN_TILE;
+}
+
 int64_t computed_pairs_per_sample(int nin, int tile, int acc)
 {
+    // whole-channel kernel: all 36 blocks of the 8x8-block triangle, whatever nin
+    if (tile == CHAN_TILE) return 36 * 32 * 32;
     const int64_t nts = (nin + tile - 1) / tile;
     if (acc == ACC_F32_CMAC) return nts * (nts + 1) / 2 * (int64_t)tile * tile;
     // MFMA kernels: 32x32 blocks, skipping blocks strictly above the diagonal of a diagonal
@@ -132,15 +139,24 @@ int make_plan(int nstation, int npol, int nchan, int ntime, int in_fmt, int acc,
     p.max_abs = in_fmt == IN_CF32 ? 0 : max_abs;
     p.nin = (int)nin64;
     int tile = acc == ACC_F32_CMAC ? 64 : (p.nin > 64 ? 128 : 64);
+    // Above 192 inputs the whole-channel kernel computes at most 36/28 of the useful blocks
+    // and reads every sample once, in whole rows.
+    if (chan_kernel_ok(p.nin, in_fmt, acc) && p.nin > 192) tile = CHAN_TILE;
     if (tile_override) {
-        if (acc == ACC_F32_CMAC ? tile_override != 64 : (tile_override != 64 && tile_override != 128)) {
-            *err = "unsupported tile size";
+        bool ok;
+        if (acc == ACC_F32_CMAC) ok = tile_override == 64;
+        else if (tile_override == CHAN_TILE) ok = chan_kernel_ok(p.nin, in_fmt, acc);
+        else ok = tile_override == 64 || tile_override == 128;
+        if (!ok) {
+            *err = tile_override == CHAN_TILE
+                       ? "tile 256 (whole channel) needs CI8 input, the int8 or fp16 path and nin <= 256, a multiple of 8"
+                       : "unsupported tile size";
             return XCORR_ERR_INVALID_ARG;
         }
         tile = tile_override;
     }
     p.tile = tile;
-    p.ntile_side = (p.nin + tile - 1) / tile;
+    p.ntile_side = tile == CHAN_TILE ? 1 : (p.nin + tile - 1) / tile;
     p.tiles_per_chan = p.ntile_side * (p.ntile_side + 1) / 2;
 
     const int64_t lim = window_limit(in_fmt, acc, in_fmt == IN_CF32 ? 1 : max_abs);

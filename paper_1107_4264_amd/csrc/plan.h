@@ -28,6 +28,13 @@ int default_max_abs(int in_fmt, int acc);
 int make_plan(int nstation, int npol, int nchan, int ntime, int in_fmt, int acc, int max_abs,
               int tile_override, Plan *pl, std::string *err);
 
+// Tile value of the whole-channel kernel: one workgroup holds the triangle of up to 256
+// inputs of a channel.
+constexpr int CHAN_TILE = 256;
+
+// Whether the whole-channel kernel accepts a job of nin inputs.
+bool chan_kernel_ok(int nin, int in_fmt, int acc);
+
 // Exact inverse of g = by*(by+1)/2 + bx, 0 <= bx <= by.
 void tile_coords(int64_t g, int64_t *bx, int64_t *by);
 

@@ -46,6 +46,9 @@ struct XItem {
 int launch_mfma(const XJob &job, int acc, int in_fmt, hipStream_t stream);
 int launch_cmac(const XJob &job, int in_fmt, hipStream_t stream);
 int launch_zero(void *ptr, size_t bytes, hipStream_t stream);
+// Whole-channel kernel (tile 256): persistent, job.grid workgroups of 512 threads walk the
+// job.nitems (channel, window) items, window-major.
+int launch_chan(const XJob &job, int acc, hipStream_t stream);
 
 // Batched persistent launch.  The work list is split into NQUEUE queues (one per XCD: a
 // channel's items all go to one queue); workgroup b takes items from queue b % NQUEUE

@@ -1,0 +1,512 @@
+// Whole-channel X-engine on the CDNA4 matrix cores (gfx950) for arrays of up to 256
+// complex 8-bit inputs.
+//
+// For such arrays one workgroup owns all the baselines of a channel (the whole lower
+// triangle of Eq. 4 at 32x32 block granularity: 8 block rows, 36 blocks), so every input
+// sample is read from HBM exactly once, as whole 512-byte rows of the [time][channel]
+// [input] layout of Sec. 5.1; splitting a row between tiles costs half the bandwidth on
+// this memory system.  The workgroup is persistent: it walks channels (and accumulation
+// windows) blockIdx.x, blockIdx.x + gridDim.x, ... with one workgroup per compute unit.
+//
+// Data path for one block of 64 time rows:
+//   * the rows are copied from HBM straight into a four-block LDS ring by buffer loads
+//     with the LDS-destination bit (no registers involved), three blocks ahead of the
+//     block being multiplied; the 16-byte chunks of a row are XOR-swizzled by the row
+//     index so that the transposing reads below are free of bank conflicts;
+//   * MFMA operands are read with ds_read_b64_tr_b16: one complex 8-bit sample is one
+//     16-bit element, so the transposing read hands each lane four consecutive samples of
+//     one input, which is the operand layout of a 32-row MFMA fragment;
+//   * the complex product is mapped to real MFMAs as in the tiled kernel: the real part is
+//     the product of the (re, im) pair sequences and the imaginary part the product with
+//     the column pairs rotated to (-im, re) (Eq. 5, four real MACs per complex MAC);
+//     the fp16 path converts the int8 pairs exactly to fp16 while forming the operands.
+// Work split (register level of the hierarchy of Sec. 4.1): four waves, one per SIMD, nine
+// 32x32 blocks each: block rows {5,6,7} x columns {0,1,2}, rows {2,3,4} x columns {0,1,2},
+// rows {5,6,7} x columns {3,4,5}, and the three diagonal triangles of rows {0,1}, {3,4},
+// {6,7}.  Every wave issues 18 MFMAs per K-step from six operand fragments.
+
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "xeng.h"
+#include "xeng_dev.h"
+
+#pragma clang diagnostic ignored "-Winline-asm"
+
+namespace xc {
+namespace {
+
+using namespace dev;
+
+constexpr int CT = 512;                         // eight waves, two per SIMD
+constexpr int CROW = 512;                       // LDS bytes per time row (256 inputs)
+constexpr int CTB = 64;                         // time rows per block
+constexpr int CRING = 4;                        // blocks in the LDS ring
+constexpr int CBLK = CTB * CROW;                // 32 KiB
+constexpr int CLDS = CRING * CBLK;              // 128 KiB
+constexpr int DMA_PER_WAVE = CTB / 2 / (CT / 64);  // each DMA instruction fills two rows
+constexpr uint32_t COOB = 0xFFFFFFF0u;          // offset beyond every descriptor
+
+template <int ACC>
+struct COp;
+// KS: samples per K-step; NREAD: transposing reads per fragment (4 samples each).
+template <>
+struct COp<ACC_I8> {
+    static constexpr int KS = 16, NREAD = 2;
+    using acc_t = i32x16;
+};
+template <>
+struct COp<ACC_F16> {
+    static constexpr int KS = 8, NREAD = 1;
+    using acc_t = f32x16;
+};
+
+typedef int i32x4s __attribute__((ext_vector_type(4)));
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) s16x4 lds_s16x4;
+
+// One row pair of a block: lane l copies 16 bytes at `voff` of the descriptor to LDS byte
+// lds + 16 l.  Issued as inline assembly so that the compiler does not drain the whole
+// ring (vmcnt 0) before every LDS read; completion is awaited explicitly (wait_dma).
+__device__ __forceinline__ void dma16(i32x4s rsrc, uint32_t lds, uint32_t voff)
+{
+    asm volatile("s_mov_b32 m0, %0\n\tbuffer_load_dwordx4 %1, %2, 0 offen lds" ::"s"(lds), "v"(voff), "s"(rsrc)
+                 : "memory", "m0");
+}
+
+// s_waitcnt vmcnt(N) (other counters untouched), N <= 63.
+template <int N>
+__device__ __forceinline__ void wait_vm()
+{
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
+// ---------------------------------------------------------------- operands
+
+template <int ACC>
+struct Raw {
+    uint32_t w[2 * COp<ACC>::NREAD];
+};
+
+// f16 operand words of a raw fragment: (re, im) and the rotated (-im, re), exactly.
+__device__ __forceinline__ void f16_pairs(uint32_t w, uint32_t &p0, uint32_t &p1)
+{
+    ci8x2_to_f16(w, p0, p1);
+}
+
+__device__ __forceinline__ void f16_rot_pairs(uint32_t w, uint32_t &p0, uint32_t &p1)
+{
+    // bytes (1152 + im, 1152 + re) as fp16, then (-(1152 + im) + 1152, (1152 + re) - 1152)
+    const uint32_t x = w ^ 0x80808080u;
+    const uint32_t a = __builtin_amdgcn_perm(0x64646464u, x, 0x04000401u);
+    const uint32_t b = __builtin_amdgcn_perm(0x64646464u, x, 0x04020403u);
+    const f16x2 sgn = {(_Float16)(-1.0f), (_Float16)1.0f};
+    const f16x2 off = {(_Float16)1152.0f, (_Float16)(-1152.0f)};
+    p0 = __builtin_bit_cast(uint32_t, __builtin_bit_cast(f16x2, a) * sgn + off);
+    p1 = __builtin_bit_cast(uint32_t, __builtin_bit_cast(f16x2, b) * sgn + off);
+}
+
+template <int ACC>
+__device__ __forceinline__ Frag<4> op_plain(const Raw<ACC> &r)
+{
+    Frag<4> o;
+    if constexpr (ACC == ACC_I8) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) o.w[k] = r.w[k];
+    } else {
+        f16_pairs(r.w[0], o.w[0], o.w[1]);
+        f16_pairs(r.w[1], o.w[2], o.w[3]);
+    }
+    return o;
+}
+
+template <int ACC>
+__device__ __forceinline__ Frag<4> op_rot(const Raw<ACC> &r)
+{
+    Frag<4> o;
+    if constexpr (ACC == ACC_I8) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) o.w[k] = rotate_pairs<ACC_I8>(r.w[k]);
+    } else {
+        f16_rot_pairs(r.w[0], o.w[0], o.w[1]);
+        f16_rot_pairs(r.w[1], o.w[2], o.w[3]);
+    }
+    return o;
+}
+
+// Transposing reads of the fragment of block row R for K-step KSTEP from the ring slot
+// whose per-lane addresses are lv[] (see lane_bases).
+template <int ACC, int R, int KSTEP>
+__device__ __forceinline__ Raw<ACC> read_frag(const uint32_t (&lv)[4])
+{
+    using O = COp<ACC>;
+    Raw<ACC> r;
+#pragma unroll
+    for (int e = 0; e < O::NREAD; ++e) {
+        const uint32_t imm = (uint32_t)((KSTEP * O::KS + 4 * e) * CROW + 256 * (R >> 2));
+        const s16x4 v = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4 *)(uintptr_t)(lv[R & 3] + imm));
+        const uint2 u = __builtin_bit_cast(uint2, v);
+        r.w[2 * e] = u.x;
+        r.w[2 * e + 1] = u.y;
+    }
+    return r;
+}
+
+// Per-lane byte offsets (within a ring slot) of the transposing reads.  Lane l = 16g + 4k + a
+// points at time row 4k' + k of its half (h = l / 32 selects samples 4*NREAD*h ..), input
+// 32R + 16(g % 2) + 4a; chunk c = 4R + 2(g % 2) + a / 2 of the row sits at chunk c ^ 4k,
+// i.e. at 4(R ^ k) + j: for R & 3 = q that is 64(q ^ k) + 16j, plus 256 for R >= 4.
+template <int ACC>
+__device__ __forceinline__ uint32_t lane_base(int lane, int q)
+{
+    using O = COp<ACC>;
+    const int h = lane >> 5;
+    const int k = (lane >> 2) & 3;
+    const int j = 2 * ((lane >> 4) & 1) + ((lane & 3) >> 1);
+    return (uint32_t)(h * 4 * O::NREAD * CROW + k * CROW + 64 * (q ^ k) + 16 * j + 8 * (lane & 1));
+}
+
+// ---------------------------------------------------------------- epilogue
+
+// Store one 32x32 block with top-left input (row0, col0): lanes hold column col0 + lane % 32,
+// register k holds row row0 + 8(k / 4) + 4(lane / 32) + k % 4.  Entries with an input
+// beyond nin or with station s1 < s2 (the upper part of a diagonal block) are skipped.
+template <int ACC>
+__device__ __forceinline__ void store_block(void *out_ptr, int nin, int npol, int accumulate, int f, int row0,
+                                            int col0, int lane, const typename COp<ACC>::acc_t &re,
+                                            const typename COp<ACC>::acc_t &im)
+{
+    using val_t = typename std::conditional<ACC == ACC_I8, int, float>::type;
+    if (row0 >= nin || col0 >= nin) return;
+    const int r32 = lane & 31, half = lane >> 5;
+    const int64_t nbl = (int64_t)(nin / npol) * (nin / npol + 1) / 2;
+    const int j = col0 + r32;
+    if (npol == 2 && !accumulate) {
+        // lanes 2k, 2k+1 hold pols q = 0, 1 of one station; registers k, k+1 rows p = 0, 1:
+        // after one exchange each lane stores the 16 bytes of one p row
+        const bool odd = lane & 1;
+        const int s2 = j >> 1;
+#pragma unroll
+        for (int k = 0; k < 16; k += 2) {
+            const int i = row0 + 8 * (k >> 2) + 4 * half + (k & 3);
+            const int s1 = i >> 1;
+            const val_t r0 = (val_t)re[k], r1 = (val_t)re[k + 1];
+            const val_t m0 = (val_t)im[k], m1 = (val_t)im[k + 1];
+            const val_t xr = swap_pair_lanes(odd ? r0 : r1);
+            const val_t xm = swap_pair_lanes(odd ? m0 : m1);
+            if (i >= nin || j >= nin || s1 < s2) continue;
+            const int64_t o = ((int64_t)f * nbl + (int64_t)s1 * (s1 + 1) / 2 + s2) * 8 + (odd ? 4 : 0);
+            if constexpr (ACC == ACC_I8) {
+                const i32x4v v = odd ? (i32x4v){xr, xm, r1, m1} : (i32x4v){r0, m0, xr, xm};
+                __builtin_nontemporal_store(v, (i32x4v *)((int *)out_ptr + o));
+            } else {
+                const f32x4 v = odd ? (f32x4){xr, xm, r1, m1} : (f32x4){r0, m0, xr, xm};
+                __builtin_nontemporal_store(v, (f32x4 *)((float *)out_ptr + o));
+            }
+        }
+        return;
+    }
+    if (j >= nin) return;
+    const int npp = npol * npol;
+    const int s2 = j / npol, q = j - s2 * npol;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const int i = row0 + 8 * (k >> 2) + 4 * half + (k & 3);
+        if (i >= nin) continue;
+        const int s1 = i / npol, pp = i - s1 * npol;
+        if (s1 < s2) continue;
+        const int64_t o = (((int64_t)f * nbl + (int64_t)s1 * (s1 + 1) / 2 + s2) * npp + pp * npol + q) * 2;
+        if constexpr (ACC == ACC_I8) {
+            if (accumulate) {
+                unsigned long long *out = (unsigned long long *)out_ptr;
+                atomicAdd(&out[o], (unsigned long long)(long long)re[k]);
+                atomicAdd(&out[o + 1], (unsigned long long)(long long)im[k]);
+            } else {
+                *(int2 *)((int *)out_ptr + o) = make_int2(re[k], im[k]);
+            }
+        } else {
+            if (accumulate) {
+                double *out = (double *)out_ptr;
+                atomicAdd(&out[o], (double)re[k]);
+                atomicAdd(&out[o + 1], (double)im[k]);
+            } else {
+                *(float2 *)((float *)out_ptr + o) = make_float2(re[k], im[k]);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- work walk
+
+// Position of a workgroup in its list of (channel, window) items, window-major so that
+// concurrent workgroups read neighbouring channels of the same time rows.  All fields are
+// wave-uniform.
+struct Cursor {
+    int64_t item;
+    int blk, nblk, f, t0, t1;
+
+    __device__ __forceinline__ void set(const XJob &p, int64_t it)
+    {
+        item = it;
+        blk = 0;
+        if (it < p.nitems) {
+            const int w = (int)(it / p.nchan);
+            f = (int)(it - (int64_t)w * p.nchan);
+            t0 = w * p.window;
+            t1 = min(p.ntime, t0 + p.window);
+            nblk = (t1 - t0 + CTB - 1) / CTB;
+        } else {
+            f = 0;
+            t0 = t1 = 0;
+            nblk = 1;
+        }
+    }
+    __device__ __forceinline__ void next(const XJob &p, int64_t stride)
+    {
+        if (++blk == nblk) set(p, item + stride);
+    }
+};
+
+// Descriptor of the block the cursor points at: rows t0 + 64 blk .. of channel f; rows past
+// the window (and everything past the last item) read as zero.
+__device__ __forceinline__ i32x4s block_rsrc(const XJob &p, const Cursor &c, uint64_t row_stride)
+{
+    const int r0 = c.t0 + c.blk * CTB;
+    const int nrows = max(0, min(CTB, c.t1 - r0));
+    const uint64_t base = (uint64_t)p.in + ((uint64_t)r0 * p.nchan + c.f) * (uint64_t)p.nin * 2;
+    const uint32_t nrec = nrows ? (uint32_t)((nrows - 1) * row_stride + (uint64_t)p.nin * 2) : 0u;
+    i32x4s r;
+    r[0] = __builtin_amdgcn_readfirstlane((int)(uint32_t)base);
+    r[1] = __builtin_amdgcn_readfirstlane((int)((uint32_t)(base >> 32) & 0xFFFFu));
+    r[2] = __builtin_amdgcn_readfirstlane((int)nrec);
+    r[3] = 0x00020000;
+    return r;
+}
+
+// ---------------------------------------------------------------- wave work lists
+
+// The 36 blocks of the triangle over eight waves, two per SIMD (waves w and w + 4 share a
+// SIMD, so each SIMD carries nine blocks of MFMA work):
+//   waves 0..3: the diagonal 2x2 triangle of block rows {2i, 2i+1} plus a two-block strip
+//               that reuses two of its fragments: row 2 / 3 x columns {0,1} (i = 0, 1),
+//               row 6 / 7 x columns {4,5} (i = 2, 3);
+//   waves 4..7: the off-diagonal 2x2 squares rows {4,5} / {6,7} x columns {0,1} / {2,3}.
+// F: block rows of the fragments a wave reads; BR/BC: per block, the fragment (index into
+// F) of its rows and of its columns; ROT: fragments also needed in rotated form (columns).
+template <int W>
+struct Spec;
+template <>
+struct Spec<0> {
+    static constexpr int NF = 3, NB = 5;
+    static constexpr int F[4] = {0, 1, 2, 0}, BR[5] = {0, 1, 1, 2, 2}, BC[5] = {0, 0, 1, 0, 1};
+    static constexpr bool ROT[4] = {true, true, false, false};
+};
+template <>
+struct Spec<1> {
+    static constexpr int NF = 4, NB = 5;
+    static constexpr int F[4] = {2, 3, 0, 1}, BR[5] = {0, 1, 1, 1, 1}, BC[5] = {0, 0, 1, 2, 3};
+    static constexpr bool ROT[4] = {true, true, true, true};
+};
+template <>
+struct Spec<2> {
+    static constexpr int NF = 3, NB = 5;
+    static constexpr int F[4] = {4, 5, 6, 0}, BR[5] = {0, 1, 1, 2, 2}, BC[5] = {0, 0, 1, 0, 1};
+    static constexpr bool ROT[4] = {true, true, false, false};
+};
+template <>
+struct Spec<3> {
+    static constexpr int NF = 4, NB = 5;
+    static constexpr int F[4] = {6, 7, 4, 5}, BR[5] = {0, 1, 1, 1, 1}, BC[5] = {0, 0, 1, 2, 3};
+    static constexpr bool ROT[4] = {true, true, true, true};
+};
+template <int I, int J>
+struct SquareSpec {
+    static constexpr int NF = 4, NB = 4;
+    static constexpr int F[4] = {2 * I, 2 * I + 1, 2 * J, 2 * J + 1}, BR[5] = {0, 0, 1, 1, 0}, BC[5] = {2, 3, 2, 3, 0};
+    static constexpr bool ROT[4] = {false, false, true, true};
+};
+template <>
+struct Spec<4> : SquareSpec<2, 0> {};
+template <>
+struct Spec<5> : SquareSpec<2, 1> {};
+template <>
+struct Spec<6> : SquareSpec<3, 0> {};
+template <>
+struct Spec<7> : SquareSpec<3, 1> {};
+
+constexpr int MAXB = 5;
+
+template <int ACC>
+struct AccSet {
+    typename COp<ACC>::acc_t re[MAXB], im[MAXB];
+};
+
+// ---------------------------------------------------------------- kernel
+
+// One K-step of wave W: read its fragments, form the operands, issue 2 NB MFMAs.
+template <int ACC, int W, int KSTEP>
+__device__ __forceinline__ void kstep(const uint32_t (&lv)[4], AccSet<ACC> &acc)
+{
+    using S = Spec<W>;
+    Raw<ACC> r[S::NF];
+    static_for<S::NF>([&](auto X) __attribute__((always_inline)) {
+        constexpr int x = decltype(X)::value;
+        r[x] = read_frag<ACC, S::F[x], KSTEP>(lv);
+    });
+    Frag<4> A[S::NF], Bt[S::NF];
+    static_for<S::NF>([&](auto X) __attribute__((always_inline)) {
+        constexpr int x = decltype(X)::value;
+        A[x] = op_plain<ACC>(r[x]);
+        if constexpr (S::ROT[x]) Bt[x] = op_rot<ACC>(r[x]);
+    });
+    static_for<S::NB>([&](auto B) __attribute__((always_inline)) {
+        constexpr int b = decltype(B)::value;
+        mma(acc.re[b], A[S::BR[b]], A[S::BC[b]]);
+        mma(acc.im[b], A[S::BR[b]], Bt[S::BC[b]]);
+    });
+}
+
+template <int ACC, int W>
+__device__ __forceinline__ void store_all(const XJob &p, int f, int lane, AccSet<ACC> &acc)
+{
+    using S = Spec<W>;
+    // Opaque copies: the validity masks of the stores depend only on the lane and the array
+    // shape, and would otherwise be hoisted out of the channel loop as hundreds of live
+    // scalar lane masks.
+    int nin = p.nin, npol = p.npol, accumulate = p.accumulate, l = lane;
+    asm volatile("" : "+s"(nin), "+s"(npol), "+s"(accumulate), "+v"(l));
+    static_for<S::NB>([&](auto B) __attribute__((always_inline)) {
+        constexpr int b = decltype(B)::value;
+        store_block<ACC>(p.out, nin, npol, accumulate, f, 32 * S::F[S::BR[b]], 32 * S::F[S::BC[b]], l, acc.re[b],
+                         acc.im[b]);
+    });
+}
+
+extern __shared__ __attribute__((aligned(16))) uint8_t chan_lds[];
+
+template <int ACC, int W>
+__device__ __forceinline__ void run_wave(const XJob &p, int lane)
+{
+    using O = COp<ACC>;
+    using S = Spec<W>;
+    constexpr int NKS = CTB / O::KS;
+    const int64_t stride = gridDim.x;
+    const uint64_t row_stride = (uint64_t)p.nchan * p.nin * 2;
+    const uint32_t lds0 = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) uint8_t *)chan_lds;
+
+    // DMA: instruction m of this wave fills rows 8 W + 2m + lane / 32, physical chunk
+    // lane % 32, which holds logical chunk (lane % 32) ^ 4 (row & 3).
+    uint32_t voff[DMA_PER_WAVE];
+    const int nchunk = (p.nin * 2 + 15) / 16;
+#pragma unroll
+    for (int m = 0; m < DMA_PER_WAVE; ++m) {
+        const int row = 2 * DMA_PER_WAVE * W + 2 * m + (lane >> 5);
+        const int c = (lane & 31) ^ (4 * (row & 3));
+        voff[m] = c < nchunk ? (uint32_t)(row * row_stride + 16 * c) : COOB;
+    }
+    auto issue = [&](const Cursor &c, int slot) __attribute__((always_inline)) {
+        const i32x4s rs = block_rsrc(p, c, row_stride);
+        const uint32_t dst = lds0 + slot * CBLK + 2 * DMA_PER_WAVE * W * CROW;
+#pragma unroll
+        for (int m = 0; m < DMA_PER_WAVE; ++m) dma16(rs, dst + 2 * m * CROW, voff[m]);
+    };
+
+    uint32_t lb[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) lb[q] = lds0 + lane_base<ACC>(lane, q);
+
+    AccSet<ACC> acc;
+#pragma unroll
+    for (int x = 0; x < MAXB; ++x) {
+        acc.re[x] = (typename O::acc_t){};
+        acc.im[x] = (typename O::acc_t){};
+    }
+
+    Cursor dc, cc;
+    dc.set(p, blockIdx.x);
+    cc.set(p, blockIdx.x);
+#pragma unroll
+    for (int d = 0; d < CRING - 1; ++d) {
+        issue(dc, d);
+        dc.next(p, stride);
+    }
+    int slot = 0;
+    while (cc.item < p.nitems) {
+        // own copies of this block done (the two later blocks may still be in flight), then
+        // everyone's: the block is complete and the slot of the previous block is free
+        wait_vm<(CRING - 2) * DMA_PER_WAVE>();
+        __syncthreads();
+        issue(dc, (slot + CRING - 1) & (CRING - 1));
+        dc.next(p, stride);
+
+        uint32_t lv[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) lv[q] = lb[q] + slot * CBLK;
+        static_for<NKS>([&](auto K) __attribute__((always_inline)) { kstep<ACC, W, decltype(K)::value>(lv, acc); });
+        slot = (slot + 1) & (CRING - 1);
+
+        if (++cc.blk == cc.nblk) {
+            store_all<ACC, W>(p, cc.f, lane, acc);
+#pragma unroll
+            for (int x = 0; x < MAXB; ++x) {
+                acc.re[x] = (typename O::acc_t){};
+                acc.im[x] = (typename O::acc_t){};
+            }
+            cc.set(p, cc.item + stride);
+        }
+    }
+    // no copy into LDS may outlive the workgroup
+    wait_vm<0>();
+}
+
+template <int ACC>
+__global__ __launch_bounds__(CT, 1) void xeng_chan_kernel(XJob p)
+{
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    switch (wave) {
+    case 0: run_wave<ACC, 0>(p, lane); break;
+    case 1: run_wave<ACC, 1>(p, lane); break;
+    case 2: run_wave<ACC, 2>(p, lane); break;
+    case 3: run_wave<ACC, 3>(p, lane); break;
+    case 4: run_wave<ACC, 4>(p, lane); break;
+    case 5: run_wave<ACC, 5>(p, lane); break;
+    case 6: run_wave<ACC, 6>(p, lane); break;
+    default: run_wave<ACC, 7>(p, lane); break;
+    }
+}
+
+template <typename K>
+int allow_lds_chan(K kernel, int bytes)
+{
+    static int done = 0;
+    if (!done) {
+        const hipError_t e = hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        if (e != hipSuccess) return (int)e;
+        done = 1;
+    }
+    return 0;
+}
+
+template <int ACC>
+int launch_chan_acc(const XJob &job, hipStream_t stream)
+{
+    auto k = xeng_chan_kernel<ACC>;
+    if (int e = allow_lds_chan(k, CLDS)) return e;
+    hipLaunchKernelGGL(k, dim3((unsigned)job.grid), dim3(CT), CLDS, stream, job);
+    return (int)hipGetLastError();
+}
+
+}  // namespace
+
+int launch_chan(const XJob &job, int acc, hipStream_t stream)
+{
+    if (job.grid <= 0) return 0;
+    if (acc == ACC_I8) return launch_chan_acc<ACC_I8>(job, stream);
+    if (acc == ACC_F16) return launch_chan_acc<ACC_F16>(job, stream);
+    return (int)hipErrorInvalidValue;
+}
+
+}  // namespace xc

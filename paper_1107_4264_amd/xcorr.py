@@ -65,13 +65,15 @@ def _load():
     sig = {
         "xcorr_create": (c_vp, [c_int, c_int, c_int, c_int, c_int, c_int]),
         "xcorr_set_max_abs": (c_int, [c_vp, c_int]),
+        "xcorr_set_tile": (c_int, [c_vp, c_int]),
+        "xcorr_get_tile": (c_int, [c_vp]),
         "xcorr_run": (c_int, [c_vp, c_vp, c_vp, c_vp]),
         "xcorr_destroy": (None, [c_vp]),
         "xcorr_in_bytes": (c_sz, [c_vp]),
         "xcorr_out_bytes": (c_sz, [c_vp]),
         "xcorr_out_type": (c_int, [c_vp]),
         "xcorr_last_error": (ctypes.c_char_p, []),
-        "xcorr_plan": (c_int, [c_int, c_int, c_int, c_int, c_int, c_int, c_int, ctypes.POINTER(PlanInfo)]),
+        "xcorr_plan": (c_int, [c_int, c_int, c_int, c_int, c_int, c_int, c_int, c_int, ctypes.POINTER(PlanInfo)]),
         "xcorr_window_limit": (c_i64, [c_int, c_int, c_int]),
         "xcorr_tile_coords": (c_int, [c_i64, ctypes.POINTER(c_i64), ctypes.POINTER(c_i64)]),
         "xcorr_batch_create": (c_vp, [c_int, c_vp, c_int, c_int]),
@@ -136,6 +138,14 @@ def xcorr_set_max_abs(h, max_abs):
     return _check(_lib.xcorr_set_max_abs(h, max_abs))
 
 
+def xcorr_set_tile(h, tile):
+    return _check(_lib.xcorr_set_tile(h, tile))
+
+
+def xcorr_get_tile(h):
+    return _check(_lib.xcorr_get_tile(h))
+
+
 def xcorr_run(h, in_ptr, out_ptr, stream_ptr):
     return _check(_lib.xcorr_run(h, in_ptr, out_ptr, stream_ptr))
 
@@ -156,9 +166,9 @@ def xcorr_out_type(h):
     return _check(_lib.xcorr_out_type(h))
 
 
-def xcorr_plan(nstation, npol, nchan, ntime, in_dtype, acc_dtype, max_abs=0):
+def xcorr_plan(nstation, npol, nchan, ntime, in_dtype, acc_dtype, max_abs=0, tile=0):
     info = PlanInfo()
-    _check(_lib.xcorr_plan(nstation, npol, nchan, ntime, in_dtype, acc_dtype, max_abs, ctypes.byref(info)))
+    _check(_lib.xcorr_plan(nstation, npol, nchan, ntime, in_dtype, acc_dtype, max_abs, tile, ctypes.byref(info)))
     return info.as_dict()
 
 
@@ -276,13 +286,19 @@ class Correlator:
     """One planned job.  ``in_dtype`` / ``acc`` take the enumerators or the short names
     ('ci8', 'ci4', 'cf32' / 'f32', 'i8', 'f16', 'f8')."""
 
-    def __init__(self, nstation, npol, nchan, ntime, in_dtype="ci8", acc="f16", max_abs=None):
+    def __init__(self, nstation, npol, nchan, ntime, in_dtype="ci8", acc="f16", max_abs=None, tile=None):
         self.nstation, self.npol, self.nchan, self.ntime = nstation, npol, nchan, ntime
         self.in_dtype = IN_NAMES.get(in_dtype, in_dtype)
         self.acc = ACC_NAMES.get(acc, acc)
         self.h = xcorr_create(nstation, npol, nchan, ntime, self.in_dtype, self.acc)
         if max_abs is not None:
             xcorr_set_max_abs(self.h, int(max_abs))
+        if tile is not None:
+            xcorr_set_tile(self.h, int(tile))
+
+    @property
+    def tile(self):
+        return xcorr_get_tile(self.h)
 
     def close(self):
         if self.h:

@@ -21,8 +21,9 @@ def device():
     return torch.device("cuda:0")
 
 
-def run_xeng(x_np, nstation, npol, in_dtype, acc, max_abs=None, nchan=None):
-    """Copy x to the device, run one job, return (numpy output, out_type)."""
+def run_xeng(x_np, nstation, npol, in_dtype, acc, max_abs=None, nchan=None, tile=None):
+    """Copy x to the device, run one job (tile None: the automatic kernel shape), return
+    (numpy output, out_type)."""
     import torch
 
     from paper_1107_4264_amd import xcorr as X
@@ -31,7 +32,9 @@ def run_xeng(x_np, nstation, npol, in_dtype, acc, max_abs=None, nchan=None):
     xt = torch.from_numpy(np.ascontiguousarray(x_np)).to(dev)
     ntime = x_np.shape[0]
     nchan = x_np.shape[1] if nchan is None else nchan
-    c = X.Correlator(nstation, npol, nchan, ntime, in_dtype, acc, max_abs=max_abs)
+    c = X.Correlator(nstation, npol, nchan, ntime, in_dtype, acc, max_abs=max_abs, tile=tile)
+    if tile is not None:
+        assert c.tile == tile
     out = c.run(xt)
     torch.cuda.synchronize()
     res = out.cpu().numpy()

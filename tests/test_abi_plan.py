@@ -88,10 +88,14 @@ def test_plan_sizes_config_shapes():
     assert p["useful_cmacs"] == 2080 * 16 * 256
     assert p["in_bytes"] == 256 * 16 * 64 * 2
     assert p["out_bytes"] == 16 * 528 * 4 * 8
-    # 128 stations x 2 pol at 1024 channels: three 128-tiles per channel on the MFMA paths
+    # 128 stations x 2 pol at 1024 channels: one whole-channel item per channel by default,
+    # three 128-tiles per channel on request; the same 36 blocks of 32x32 pairs either way
+    # (16 + 10 + 10 for the tiles)
     p = X.xcorr_plan(128, 2, 1024, 1000, X.IN_CI8, X.ACC_F16_MMA_F32, 18)
-    assert (p["tile"], p["ntile_side"], p["tiles_per_chan"]) == (128, 2, 3)
-    # 32x32 blocks on or below the diagonal: 16 + 10 + 10 blocks of 1024 pairs
+    assert (p["tile"], p["ntile_side"], p["tiles_per_chan"], p["nitems"]) == (256, 1, 1, 1024)
+    assert p["computed_cmacs"] == 36 * 1024 * 1024 * 1000
+    p = X.xcorr_plan(128, 2, 1024, 1000, X.IN_CI8, X.ACC_F16_MMA_F32, 18, 128)
+    assert (p["tile"], p["ntile_side"], p["tiles_per_chan"], p["nitems"]) == (128, 2, 3, 3072)
     assert p["computed_cmacs"] == 36 * 1024 * 1024 * 1000
     # 512 stations x 2 pol, 4-bit: 36 tiles per channel
     p = X.xcorr_plan(512, 2, 256, 4096, X.IN_CI4, X.ACC_I8_MMA_I32, 0)
@@ -167,3 +171,43 @@ def test_table1_model():
     assert pm.tile_ai(1, 1, 1, word=4.0) == pytest.approx(32 / 96)
     assert pm.tile_ai(1, 1, 1) == pytest.approx(gold["intensity"]["single_baseline_ai"])
     assert pm.tile_ai(8, 8, 1e9) == pytest.approx(8.0, rel=1e-6)
+
+
+@pytest.mark.parametrize("acc", [X.ACC_I8_MMA_I32, X.ACC_F16_MMA_F32])
+def test_tile_choice(acc):
+    """The whole-channel kernel (tile 256) is the default for 193..256 inputs that are a
+    multiple of 8 (16-byte rows), CI8 input and the int8 / fp16 paths."""
+    def tile(ns, npol, t=0, fmt=X.IN_CI8, a=acc):
+        return X.xcorr_plan(ns, npol, 3, 100, fmt, a, 0, t)["tile"]
+
+    assert tile(128, 2) == 256
+    assert tile(100, 2) == 256        # nin 200
+    assert tile(256, 1) == 256        # single polarisation
+    assert tile(96, 2) == 128         # nin 192: tiles
+    assert tile(127, 2) == 128        # nin 254: rows not 16-byte aligned
+    assert tile(129, 2) == 128        # nin 258
+    assert tile(128, 2, fmt=X.IN_CI4) == 128
+    assert tile(128, 2, a=X.ACC_F32_CMAC) == 64
+    # explicit shapes
+    assert tile(32, 2, 256) == 256    # allowed below the automatic threshold
+    assert tile(128, 2, 128) == 128
+    assert tile(128, 2, 64) == 64
+    for bad in [(129, 2, 256), (127, 2, 256), (64, 2, 32), (64, 2, 512)]:
+        with pytest.raises(X.XcorrError) as ei:
+            tile(*bad)
+        assert ei.value.code == X.ERR_INVALID_ARG
+    with pytest.raises(X.XcorrError):
+        tile(128, 2, 256, fmt=X.IN_CI4)
+    with pytest.raises(X.XcorrError):
+        X.xcorr_plan(128, 2, 3, 100, X.IN_CI8, X.ACC_F8E4M3_MMA_F32, 16, 256)
+    with pytest.raises(X.XcorrError):
+        X.xcorr_plan(128, 2, 3, 100, X.IN_CI8, X.ACC_F32_CMAC, 0, 256)
+
+
+def test_whole_channel_items_and_windows():
+    # one item per (channel, window); windows stay multiples of the 64-sample block
+    p = X.xcorr_plan(128, 2, 10, 70000, X.IN_CI8, X.ACC_I8_MMA_I32, 0)
+    assert p["tile"] == 256 and p["nwindows"] == 2 and p["window"] % 64 == 0
+    assert p["nitems"] == 10 * 2 and p["out_dtype"] == X.OUT_CI64
+    p = X.xcorr_plan(16, 2, 10, 100, X.IN_CI8, X.ACC_F16_MMA_F32, 0, 256)
+    assert p["computed_cmacs"] == 36 * 1024 * 10 * 100
