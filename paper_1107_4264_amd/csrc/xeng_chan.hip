@@ -41,12 +41,36 @@ using namespace dev;
 
 constexpr int CT = 512;                         // eight waves, two per SIMD
 constexpr int CROW = 512;                       // LDS bytes per time row (256 inputs)
-constexpr int CTB = 64;                         // time rows per block
-constexpr int CRING = 4;                        // blocks in the LDS ring
-constexpr int CBLK = CTB * CROW;                // 32 KiB
-constexpr int CLDS = CRING * CBLK;              // 128 KiB
-constexpr int DMA_PER_WAVE = CTB / 2 / (CT / 64);  // each DMA instruction fills two rows
 constexpr uint32_t COOB = 0xFFFFFFF0u;          // offset beyond every descriptor
+
+// Per path: TB time rows per block, RING raw blocks in the LDS ring, STAGE: the operands are
+// converted once per block into an LDS buffer (two buffers) instead of at every fragment
+// read.  The int8 path multiplies the raw pairs directly; the fp16 path converts each
+// sample once (its conversion costs more than the transposing read it replaces).
+template <int ACC>
+struct ChanCfg;
+template <>
+struct ChanCfg<ACC_I8> {
+    static constexpr int TB = 64, RING = 4;
+    static constexpr bool STAGE = false;
+};
+template <>
+struct ChanCfg<ACC_F16> {
+    static constexpr int TB = 32, RING = 5;
+    static constexpr bool STAGE = true;
+};
+template <int ACC>
+struct Geom {
+    static constexpr int TB = ChanCfg<ACC>::TB, RING = ChanCfg<ACC>::RING;
+    static constexpr bool STAGE = ChanCfg<ACC>::STAGE;
+    static constexpr int BLK = TB * CROW;                   // raw bytes per block
+    static constexpr int DPW = TB / 2 / (CT / 64);          // copies per wave per block
+    static constexpr int QUADS = TB / 4;                    // 4-sample groups per block
+    static constexpr int FBUF = STAGE ? QUADS * 256 * 16 : 0;  // staged operand bytes
+    static constexpr int LDS = RING * BLK + 2 * FBUF;
+    // conversion: 16 groups of 16 inputs x QUADS per block, four per wave instruction
+    static constexpr int NCONV = STAGE ? 16 * QUADS / 4 / (CT / 64) : 0;
+};
 
 template <int ACC>
 struct COp;
@@ -63,6 +87,7 @@ struct COp<ACC_F16> {
 };
 
 typedef int i32x4s __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef short s16x4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) s16x4 lds_s16x4;
 
@@ -90,22 +115,10 @@ struct Raw {
     uint32_t w[2 * COp<ACC>::NREAD];
 };
 
-// f16 operand words of a raw fragment: (re, im) and the rotated (-im, re), exactly.
+// fp16 operand words of a raw fragment: (re, im) pairs, exactly.
 __device__ __forceinline__ void f16_pairs(uint32_t w, uint32_t &p0, uint32_t &p1)
 {
     ci8x2_to_f16(w, p0, p1);
-}
-
-__device__ __forceinline__ void f16_rot_pairs(uint32_t w, uint32_t &p0, uint32_t &p1)
-{
-    // bytes (1152 + im, 1152 + re) as fp16, then (-(1152 + im) + 1152, (1152 + re) - 1152)
-    const uint32_t x = w ^ 0x80808080u;
-    const uint32_t a = __builtin_amdgcn_perm(0x64646464u, x, 0x04000401u);
-    const uint32_t b = __builtin_amdgcn_perm(0x64646464u, x, 0x04020403u);
-    const f16x2 sgn = {(_Float16)(-1.0f), (_Float16)1.0f};
-    const f16x2 off = {(_Float16)1152.0f, (_Float16)(-1152.0f)};
-    p0 = __builtin_bit_cast(uint32_t, __builtin_bit_cast(f16x2, a) * sgn + off);
-    p1 = __builtin_bit_cast(uint32_t, __builtin_bit_cast(f16x2, b) * sgn + off);
 }
 
 template <int ACC>
@@ -122,16 +135,30 @@ __device__ __forceinline__ Frag<4> op_plain(const Raw<ACC> &r)
     return o;
 }
 
-template <int ACC>
-__device__ __forceinline__ Frag<4> op_rot(const Raw<ACC> &r)
+// Rotated operands for the imaginary part, Im V_ij = sum_t (im_i re_j - re_i im_j): either
+// the column operand as (-im, re) pairs (COL) or the row operand as (im, -re) pairs, from the
+// plain operand words (int8 pairs or fp16 pairs), exactly.
+template <int ACC, bool COL>
+__device__ __forceinline__ Frag<4> op_rot(const Frag<4> &a)
 {
     Frag<4> o;
-    if constexpr (ACC == ACC_I8) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) o.w[k] = rotate_pairs<ACC_I8>(r.w[k]);
-    } else {
-        f16_rot_pairs(r.w[0], o.w[0], o.w[1]);
-        f16_rot_pairs(r.w[1], o.w[2], o.w[3]);
+    for (int k = 0; k < 4; ++k) {
+        if constexpr (ACC == ACC_I8) {
+            if constexpr (COL) {
+                o.w[k] = rotate_pairs<ACC_I8>(a.w[k]);
+            } else {
+                // [im, re] per pair, then the high byte negated: (~re + 1) with the carry
+                // leaving the 16-bit lane
+                const uint32_t sw = __builtin_amdgcn_perm(a.w[k], a.w[k], 0x02030001u);
+                const i16x2 v = __builtin_bit_cast(i16x2, sw ^ 0xFF00FF00u) + (i16x2){0x0100, 0x0100};
+                o.w[k] = __builtin_bit_cast(uint32_t, v);
+            }
+        } else {
+            const f16x2 v = __builtin_bit_cast(f16x2, a.w[k]);
+            const f16x2 sgn = COL ? (f16x2){(_Float16)(-1.0f), (_Float16)1.0f} : (f16x2){(_Float16)1.0f, (_Float16)(-1.0f)};
+            o.w[k] = __builtin_bit_cast(uint32_t, __builtin_shufflevector(v, v, 1, 0) * sgn);
+        }
     }
     return o;
 }
@@ -173,12 +200,14 @@ __device__ __forceinline__ uint32_t lane_base(int lane, int q)
 // Store one 32x32 block with top-left input (row0, col0): lanes hold column col0 + lane % 32,
 // register k holds row row0 + 8(k / 4) + 4(lane / 32) + k % 4.  Entries with an input
 // beyond nin or with station s1 < s2 (the upper part of a diagonal block) are skipped.
+// accumulate: add into the wide output with atomics (sums of windows).
 template <int ACC>
 __device__ __forceinline__ void store_block(void *out_ptr, int nin, int npol, int accumulate, int f, int row0,
                                             int col0, int lane, const typename COp<ACC>::acc_t &re,
                                             const typename COp<ACC>::acc_t &im)
 {
     using val_t = typename std::conditional<ACC == ACC_I8, int, float>::type;
+    using vec4_t = typename std::conditional<ACC == ACC_I8, i32x4v, f32x4>::type;
     if (row0 >= nin || col0 >= nin) return;
     const int r32 = lane & 31, half = lane >> 5;
     const int64_t nbl = (int64_t)(nin / npol) * (nin / npol + 1) / 2;
@@ -187,6 +216,7 @@ __device__ __forceinline__ void store_block(void *out_ptr, int nin, int npol, in
         // lanes 2k, 2k+1 hold pols q = 0, 1 of one station; registers k, k+1 rows p = 0, 1:
         // after one exchange each lane stores the 16 bytes of one p row
         const bool odd = lane & 1;
+        const int om = odd_lane_mask(lane);
         const int s2 = j >> 1;
 #pragma unroll
         for (int k = 0; k < 16; k += 2) {
@@ -194,17 +224,12 @@ __device__ __forceinline__ void store_block(void *out_ptr, int nin, int npol, in
             const int s1 = i >> 1;
             const val_t r0 = (val_t)re[k], r1 = (val_t)re[k + 1];
             const val_t m0 = (val_t)im[k], m1 = (val_t)im[k + 1];
-            const val_t xr = swap_pair_lanes(odd ? r0 : r1);
-            const val_t xm = swap_pair_lanes(odd ? m0 : m1);
+            const val_t xr = swap_pair_lanes(pair_send(r0, r1, om));
+            const val_t xm = swap_pair_lanes(pair_send(m0, m1, om));
             if (i >= nin || j >= nin || s1 < s2) continue;
             const int64_t o = ((int64_t)f * nbl + (int64_t)s1 * (s1 + 1) / 2 + s2) * 8 + (odd ? 4 : 0);
-            if constexpr (ACC == ACC_I8) {
-                const i32x4v v = odd ? (i32x4v){xr, xm, r1, m1} : (i32x4v){r0, m0, xr, xm};
-                __builtin_nontemporal_store(v, (i32x4v *)((int *)out_ptr + o));
-            } else {
-                const f32x4 v = odd ? (f32x4){xr, xm, r1, m1} : (f32x4){r0, m0, xr, xm};
-                __builtin_nontemporal_store(v, (f32x4 *)((float *)out_ptr + o));
-            }
+            const vec4_t v = odd ? (vec4_t){xr, xm, r1, m1} : (vec4_t){r0, m0, xr, xm};
+            __builtin_nontemporal_store(v, (vec4_t *)((val_t *)out_ptr + o));
         }
         return;
     }
@@ -238,43 +263,117 @@ __device__ __forceinline__ void store_block(void *out_ptr, int nin, int npol, in
     }
 }
 
+// a <- (a lanes 0..31, b lanes 0..31), b <- (a lanes 32..63, b lanes 32..63).
+__device__ __forceinline__ void lane_swap32(uint32_t &a, uint32_t &b)
+{
+    const auto r = __builtin_amdgcn_permlane32_swap(a, b, false, false);
+    a = r[0];
+    b = r[1];
+}
+
+__device__ __forceinline__ uint32_t bits32(int x) { return (uint32_t)x; }
+__device__ __forceinline__ uint32_t bits32(float x) { return __builtin_bit_cast(uint32_t, x); }
+
+// Pair exchange of registers k, k + 1 of one block (as in store_block): the even lane gets
+// the 16 bytes of slots (0,0), (0,1) of its station pair, the odd lane (1,0), (1,1).
+template <int ACC>
+__device__ __forceinline__ void exchange_pair(const typename COp<ACC>::acc_t &re, const typename COp<ACC>::acc_t &im,
+                                              int k, int om, bool odd, uint32_t (&v)[4])
+{
+    // element copies first: a bit cast of a vector element subscript reads element 0 with
+    // this compiler
+    const uint32_t r0 = bits32(re[k]), r1 = bits32(re[k + 1]);
+    const uint32_t m0 = bits32(im[k]), m1 = bits32(im[k + 1]);
+    const uint32_t xr = (uint32_t)swap_pair_lanes(pair_send((int)r0, (int)r1, om));
+    const uint32_t xm = (uint32_t)swap_pair_lanes(pair_send((int)m0, (int)m1, om));
+    v[0] = odd ? xr : r0;
+    v[1] = odd ? xm : m0;
+    v[2] = odd ? r1 : xr;
+    v[3] = odd ? m1 : xm;
+}
+
+// Store two horizontally adjacent 32x32 blocks (columns col0 .. col0 + 63) when there are
+// two polarisations and no window sums: after the pair exchange of store_block, one lane
+// swap between the blocks (lanes 32..63 of the left block with lanes 0..31 of the right
+// one) leaves each register with one row of 64 consecutive inputs, 32 stations, so that
+// every store instruction writes 1 KiB of consecutive baselines.
+template <int ACC>
+__device__ __forceinline__ void store_pair(void *out_ptr, int nin, int f, int row0, int col0, int lane,
+                                           const typename COp<ACC>::acc_t &re1, const typename COp<ACC>::acc_t &im1,
+                                           const typename COp<ACC>::acc_t &re2, const typename COp<ACC>::acc_t &im2)
+{
+    using val_t = typename std::conditional<ACC == ACC_I8, int, float>::type;
+    using vec4_t = typename std::conditional<ACC == ACC_I8, i32x4v, f32x4>::type;
+    if (row0 >= nin || col0 >= nin) return;
+    const int64_t nbl = (int64_t)(nin / 2) * (nin / 2 + 1) / 2;
+    const bool odd = lane & 1;
+    const int om = odd_lane_mask(lane);
+    const int j = col0 + lane, s2 = j >> 1;
+#pragma unroll
+    for (int k = 0; k < 16; k += 2) {
+        // pair exchange in each block (as in store_block): the even lane gets slots (0,0),
+        // (0,1) of its station pair, the odd lane (1,0), (1,1)
+        uint32_t v[2][4];
+        exchange_pair<ACC>(re1, im1, k, om, odd, v[0]);
+        exchange_pair<ACC>(re2, im2, k, om, odd, v[1]);
+        // after the swap v[0] holds row i and v[1] row i + 4, columns col0 + lane
+#pragma unroll
+        for (int c = 0; c < 4; ++c) lane_swap32(v[0][c], v[1][c]);
+        const int i = row0 + 8 * (k >> 2) + (k & 3);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int ih = i + 4 * h, s1 = ih >> 1;
+            if (ih >= nin || j >= nin || s1 < s2) continue;
+            const int64_t o = ((int64_t)f * nbl + (int64_t)s1 * (s1 + 1) / 2 + s2) * 8 + (odd ? 4 : 0);
+            const vec4_t w = __builtin_bit_cast(vec4_t, (u32x4){v[h][0], v[h][1], v[h][2], v[h][3]});
+            __builtin_nontemporal_store(w, (vec4_t *)((val_t *)out_ptr + o));
+        }
+    }
+}
+
 // ---------------------------------------------------------------- work walk
 
-// Position of a workgroup in its list of (channel, window) items, window-major so that
-// concurrent workgroups read neighbouring channels of the same time rows.  All fields are
-// wave-uniform.
+// Position of a workgroup in its work: the (channel, window) items blockIdx.x,
+// blockIdx.x + gridDim.x, ... (window-major, so that concurrent workgroups read
+// neighbouring channels of the same time rows), walked one time block at a time.  All
+// fields are wave-uniform.
+template <int TB>
 struct Cursor {
     int64_t item;
     int blk, nblk, f, t0, t1;
+    bool valid;
 
     __device__ __forceinline__ void set(const XJob &p, int64_t it)
     {
         item = it;
         blk = 0;
-        if (it < p.nitems) {
+        valid = it < p.nitems;
+        if (valid) {
             const int w = (int)(it / p.nchan);
             f = (int)(it - (int64_t)w * p.nchan);
             t0 = w * p.window;
             t1 = min(p.ntime, t0 + p.window);
-            nblk = (t1 - t0 + CTB - 1) / CTB;
-        } else {
+            nblk = (t1 - t0 + TB - 1) / TB;
+        } else {  // past the end: empty blocks
             f = 0;
             t0 = t1 = 0;
             nblk = 1;
         }
     }
-    __device__ __forceinline__ void next(const XJob &p, int64_t stride)
+    __device__ __forceinline__ void init(const XJob &p) { set(p, blockIdx.x); }
+    __device__ __forceinline__ void next(const XJob &p)
     {
-        if (++blk == nblk) set(p, item + stride);
+        if (++blk == nblk) set(p, item + gridDim.x);
     }
 };
 
-// Descriptor of the block the cursor points at: rows t0 + 64 blk .. of channel f; rows past
+// Descriptor of the block the cursor points at: rows t0 + TB blk .. of channel f; rows past
 // the window (and everything past the last item) read as zero.
-__device__ __forceinline__ i32x4s block_rsrc(const XJob &p, const Cursor &c, uint64_t row_stride)
+template <int TB>
+__device__ __forceinline__ i32x4s block_rsrc(const XJob &p, const Cursor<TB> &c, uint64_t row_stride)
 {
-    const int r0 = c.t0 + c.blk * CTB;
-    const int nrows = max(0, min(CTB, c.t1 - r0));
+    const int r0 = c.t0 + c.blk * TB;
+    const int nrows = max(0, min(TB, c.t1 - r0));
     const uint64_t base = (uint64_t)p.in + ((uint64_t)r0 * p.nchan + c.f) * (uint64_t)p.nin * 2;
     const uint32_t nrec = nrows ? (uint32_t)((nrows - 1) * row_stride + (uint64_t)p.nin * 2) : 0u;
     i32x4s r;
@@ -294,7 +393,10 @@ __device__ __forceinline__ i32x4s block_rsrc(const XJob &p, const Cursor &c, uin
 //               row 6 / 7 x columns {4,5} (i = 2, 3);
 //   waves 4..7: the off-diagonal 2x2 squares rows {4,5} / {6,7} x columns {0,1} / {2,3}.
 // F: block rows of the fragments a wave reads; BR/BC: per block, the fragment (index into
-// F) of its rows and of its columns; ROT: fragments also needed in rotated form (columns).
+// F) of its rows and of its columns; ROT: fragments also needed in rotated form, the
+// columns, or with ROWROT the rows (waves 1 and 3 have two row and four column fragments).
+// PAIR: blocks b whose right neighbour (same block row, next block column) is block b + 1,
+// stored together; SINGLE: the block without a neighbour (-1: none).
 template <int W>
 struct Spec;
 template <>
@@ -302,30 +404,40 @@ struct Spec<0> {
     static constexpr int NF = 3, NB = 5;
     static constexpr int F[4] = {0, 1, 2, 0}, BR[5] = {0, 1, 1, 2, 2}, BC[5] = {0, 0, 1, 0, 1};
     static constexpr bool ROT[4] = {true, true, false, false};
+    static constexpr bool ROWROT = false;
+    static constexpr int NPAIR = 2, PAIR[2] = {1, 3}, SINGLE = 0;
 };
 template <>
 struct Spec<1> {
     static constexpr int NF = 4, NB = 5;
     static constexpr int F[4] = {2, 3, 0, 1}, BR[5] = {0, 1, 1, 1, 1}, BC[5] = {0, 0, 1, 2, 3};
-    static constexpr bool ROT[4] = {true, true, true, true};
+    static constexpr bool ROT[4] = {true, true, false, false};
+    static constexpr bool ROWROT = true;
+    static constexpr int NPAIR = 2, PAIR[2] = {3, 1}, SINGLE = 0;
 };
 template <>
 struct Spec<2> {
     static constexpr int NF = 3, NB = 5;
     static constexpr int F[4] = {4, 5, 6, 0}, BR[5] = {0, 1, 1, 2, 2}, BC[5] = {0, 0, 1, 0, 1};
     static constexpr bool ROT[4] = {true, true, false, false};
+    static constexpr bool ROWROT = false;
+    static constexpr int NPAIR = 2, PAIR[2] = {1, 3}, SINGLE = 0;
 };
 template <>
 struct Spec<3> {
     static constexpr int NF = 4, NB = 5;
     static constexpr int F[4] = {6, 7, 4, 5}, BR[5] = {0, 1, 1, 1, 1}, BC[5] = {0, 0, 1, 2, 3};
-    static constexpr bool ROT[4] = {true, true, true, true};
+    static constexpr bool ROT[4] = {true, true, false, false};
+    static constexpr bool ROWROT = true;
+    static constexpr int NPAIR = 2, PAIR[2] = {3, 1}, SINGLE = 0;
 };
 template <int I, int J>
 struct SquareSpec {
     static constexpr int NF = 4, NB = 4;
     static constexpr int F[4] = {2 * I, 2 * I + 1, 2 * J, 2 * J + 1}, BR[5] = {0, 0, 1, 1, 0}, BC[5] = {2, 3, 2, 3, 0};
     static constexpr bool ROT[4] = {false, false, true, true};
+    static constexpr bool ROWROT = false;
+    static constexpr int NPAIR = 2, PAIR[2] = {0, 2}, SINGLE = -1;
 };
 template <>
 struct Spec<4> : SquareSpec<2, 0> {};
@@ -355,16 +467,17 @@ __device__ __forceinline__ void kstep(const uint32_t (&lv)[4], AccSet<ACC> &acc)
         constexpr int x = decltype(X)::value;
         r[x] = read_frag<ACC, S::F[x], KSTEP>(lv);
     });
-    Frag<4> A[S::NF], Bt[S::NF];
+    Frag<4> A[S::NF], Rt[S::NF];
     static_for<S::NF>([&](auto X) __attribute__((always_inline)) {
         constexpr int x = decltype(X)::value;
         A[x] = op_plain<ACC>(r[x]);
-        if constexpr (S::ROT[x]) Bt[x] = op_rot<ACC>(r[x]);
+        if constexpr (S::ROT[x]) Rt[x] = op_rot<ACC, !S::ROWROT>(A[x]);
     });
     static_for<S::NB>([&](auto B) __attribute__((always_inline)) {
         constexpr int b = decltype(B)::value;
         mma(acc.re[b], A[S::BR[b]], A[S::BC[b]]);
-        mma(acc.im[b], A[S::BR[b]], Bt[S::BC[b]]);
+        if constexpr (S::ROWROT) mma(acc.im[b], Rt[S::BR[b]], A[S::BC[b]]);
+        else mma(acc.im[b], A[S::BR[b]], Rt[S::BC[b]]);
     });
 }
 
@@ -377,6 +490,20 @@ __device__ __forceinline__ void store_all(const XJob &p, int f, int lane, AccSet
     // scalar lane masks.
     int nin = p.nin, npol = p.npol, accumulate = p.accumulate, l = lane;
     asm volatile("" : "+s"(nin), "+s"(npol), "+s"(accumulate), "+v"(l));
+    if (npol == 2 && !accumulate) {
+        static_for<S::NPAIR>([&](auto P) __attribute__((always_inline)) {
+            constexpr int b = S::PAIR[decltype(P)::value];
+            static_assert(S::BR[b] == S::BR[b + 1] && S::F[S::BC[b + 1]] == S::F[S::BC[b]] + 1, "adjacent pair");
+            store_pair<ACC>(p.out, nin, f, 32 * S::F[S::BR[b]], 32 * S::F[S::BC[b]], l, acc.re[b], acc.im[b],
+                            acc.re[b + 1], acc.im[b + 1]);
+        });
+        if constexpr (S::SINGLE >= 0) {
+            constexpr int b = S::SINGLE;
+            store_block<ACC>(p.out, nin, npol, accumulate, f, 32 * S::F[S::BR[b]], 32 * S::F[S::BC[b]], l, acc.re[b],
+                             acc.im[b]);
+        }
+        return;
+    }
     static_for<S::NB>([&](auto B) __attribute__((always_inline)) {
         constexpr int b = decltype(B)::value;
         store_block<ACC>(p.out, nin, npol, accumulate, f, 32 * S::F[S::BR[b]], 32 * S::F[S::BC[b]], l, acc.re[b],
@@ -386,36 +513,58 @@ __device__ __forceinline__ void store_all(const XJob &p, int f, int lane, AccSet
 
 extern __shared__ __attribute__((aligned(16))) uint8_t chan_lds[];
 
+typedef __attribute__((address_space(3))) u32x4 lds_u4;
+
+// One K-step of wave W on staged fp16 operands: fragment of block row R for K-step KSTEP at
+// lvf + 8192 KSTEP + 512 R (lvf: this lane's unit of the buffer, see run_wave).
+template <int ACC, int W, int KSTEP>
+__device__ __forceinline__ void kstep_staged(uint32_t lvf, AccSet<ACC> &acc)
+{
+    using S = Spec<W>;
+    Frag<4> A[S::NF], Rt[S::NF];
+    static_for<S::NF>([&](auto X) __attribute__((always_inline)) {
+        constexpr int x = decltype(X)::value;
+        const u32x4 v = *(const lds_u4 *)(uintptr_t)(lvf + (uint32_t)(KSTEP * 8192 + S::F[x] * 512));
+        A[x].w[0] = v[0]; A[x].w[1] = v[1]; A[x].w[2] = v[2]; A[x].w[3] = v[3];
+    });
+    static_for<S::NF>([&](auto X) __attribute__((always_inline)) {
+        constexpr int x = decltype(X)::value;
+        if constexpr (S::ROT[x]) Rt[x] = op_rot<ACC, !S::ROWROT>(A[x]);
+    });
+    static_for<S::NB>([&](auto B) __attribute__((always_inline)) {
+        constexpr int b = decltype(B)::value;
+        mma(acc.re[b], A[S::BR[b]], A[S::BC[b]]);
+        if constexpr (S::ROWROT) mma(acc.im[b], Rt[S::BR[b]], A[S::BC[b]]);
+        else mma(acc.im[b], A[S::BR[b]], Rt[S::BC[b]]);
+    });
+}
+
 template <int ACC, int W>
 __device__ __forceinline__ void run_wave(const XJob &p, int lane)
 {
     using O = COp<ACC>;
-    using S = Spec<W>;
-    constexpr int NKS = CTB / O::KS;
-    const int64_t stride = gridDim.x;
+    using G = Geom<ACC>;
+    constexpr int TB = G::TB, RING = G::RING, DPW = G::DPW;
+    constexpr int NKS = TB / O::KS;
     const uint64_t row_stride = (uint64_t)p.nchan * p.nin * 2;
     const uint32_t lds0 = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) uint8_t *)chan_lds;
 
-    // DMA: instruction m of this wave fills rows 8 W + 2m + lane / 32, physical chunk
+    // Copies: instruction m of this wave fills rows 2 DPW W + 2m + lane / 32, physical chunk
     // lane % 32, which holds logical chunk (lane % 32) ^ 4 (row & 3).
-    uint32_t voff[DMA_PER_WAVE];
+    uint32_t voff[DPW];
     const int nchunk = (p.nin * 2 + 15) / 16;
 #pragma unroll
-    for (int m = 0; m < DMA_PER_WAVE; ++m) {
-        const int row = 2 * DMA_PER_WAVE * W + 2 * m + (lane >> 5);
+    for (int m = 0; m < DPW; ++m) {
+        const int row = 2 * DPW * W + 2 * m + (lane >> 5);
         const int c = (lane & 31) ^ (4 * (row & 3));
         voff[m] = c < nchunk ? (uint32_t)(row * row_stride + 16 * c) : COOB;
     }
-    auto issue = [&](const Cursor &c, int slot) __attribute__((always_inline)) {
-        const i32x4s rs = block_rsrc(p, c, row_stride);
-        const uint32_t dst = lds0 + slot * CBLK + 2 * DMA_PER_WAVE * W * CROW;
+    auto issue = [&](const Cursor<TB> &c, int slot) __attribute__((always_inline)) {
+        const i32x4s rs = block_rsrc<TB>(p, c, row_stride);
+        const uint32_t dst = lds0 + slot * G::BLK + 2 * DPW * W * CROW;
 #pragma unroll
-        for (int m = 0; m < DMA_PER_WAVE; ++m) dma16(rs, dst + 2 * m * CROW, voff[m]);
+        for (int m = 0; m < DPW; ++m) dma16(rs, dst + 2 * m * CROW, voff[m]);
     };
-
-    uint32_t lb[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) lb[q] = lds0 + lane_base<ACC>(lane, q);
 
     AccSet<ACC> acc;
 #pragma unroll
@@ -423,38 +572,116 @@ __device__ __forceinline__ void run_wave(const XJob &p, int lane)
         acc.re[x] = (typename O::acc_t){};
         acc.im[x] = (typename O::acc_t){};
     }
-
-    Cursor dc, cc;
-    dc.set(p, blockIdx.x);
-    cc.set(p, blockIdx.x);
+    auto finish_item = [&](Cursor<TB> &cc) __attribute__((always_inline)) {
+        store_all<ACC, W>(p, cc.f, lane, acc);
 #pragma unroll
-    for (int d = 0; d < CRING - 1; ++d) {
+        for (int x = 0; x < MAXB; ++x) {
+            acc.re[x] = (typename O::acc_t){};
+            acc.im[x] = (typename O::acc_t){};
+        }
+        cc.set(p, cc.item + gridDim.x);
+    };
+
+    Cursor<TB> dc, cc;
+    dc.init(p);
+    cc.init(p);
+#pragma unroll
+    for (int d = 0; d < RING - 1; ++d) {
         issue(dc, d);
-        dc.next(p, stride);
+        dc.next(p);
     }
-    int slot = 0;
-    while (cc.item < p.nitems) {
-        // own copies of this block done (the two later blocks may still be in flight), then
-        // everyone's: the block is complete and the slot of the previous block is free
-        wait_vm<(CRING - 2) * DMA_PER_WAVE>();
-        __syncthreads();
-        issue(dc, (slot + CRING - 1) & (CRING - 1));
-        dc.next(p, stride);
 
-        uint32_t lv[4];
+    if constexpr (!G::STAGE) {
+        uint32_t lb[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) lv[q] = lb[q] + slot * CBLK;
-        static_for<NKS>([&](auto K) __attribute__((always_inline)) { kstep<ACC, W, decltype(K)::value>(lv, acc); });
-        slot = (slot + 1) & (CRING - 1);
+        for (int q = 0; q < 4; ++q) lb[q] = lds0 + lane_base<ACC>(lane, q);
+        int slot = 0;
+        int ready = 0;  // blocks known complete without a wait (copied before the last stores)
+        while (cc.valid) {
+            // own copies of this block done (the later blocks may still be in flight), then
+            // everyone's: the block is complete and the slot of the previous block is free.
+            // After an epilogue the next RING - 1 blocks were awaited before its stores;
+            // waiting on the counter would also wait for the stores.
+            if (ready == 0) wait_vm<(RING - 2) * DPW>();
+            else --ready;
+            __syncthreads();
+            issue(dc, slot == 0 ? RING - 1 : slot - 1);
+            dc.next(p);
 
-        if (++cc.blk == cc.nblk) {
-            store_all<ACC, W>(p, cc.f, lane, acc);
+            uint32_t lv[4];
 #pragma unroll
-            for (int x = 0; x < MAXB; ++x) {
-                acc.re[x] = (typename O::acc_t){};
-                acc.im[x] = (typename O::acc_t){};
+            for (int q = 0; q < 4; ++q) lv[q] = lb[q] + slot * G::BLK;
+            static_for<NKS>([&](auto K) __attribute__((always_inline)) { kstep<ACC, W, decltype(K)::value>(lv, acc); });
+            slot = slot == RING - 1 ? 0 : slot + 1;
+
+            if (++cc.blk == cc.nblk) {
+                wait_vm<0>();
+                ready = RING - 1;
+                finish_item(cc);
             }
-            cc.set(p, cc.item + stride);
+        }
+    } else {
+        // Staged operands: the block after the one being multiplied is converted into the
+        // other buffer (unit of input i and samples 4q..4q+3 at 4096 q + 16 i), read from the
+        // raw ring with transposing reads: instruction u of this wave covers 16-input groups
+        // ig = c % 16 at sample groups q = c / 16, c = 4 (NCONV W + u) + lane / 16.
+        const uint32_t fb0 = lds0 + RING * G::BLK;
+        uint32_t cin[G::NCONV], cout[G::NCONV];
+#pragma unroll
+        for (int u = 0; u < G::NCONV; ++u) {
+            const int c = 4 * (G::NCONV * W + u) + (lane >> 4);
+            const int ig = c & 15, q = c >> 4;
+            const int k = (lane >> 2) & 3, a = lane & 3;
+            const int row = 4 * q + k;
+            const int chunk = (2 * ig + (a >> 1)) ^ (4 * k);
+            cin[u] = (uint32_t)(row * CROW + 16 * chunk + 8 * (a & 1));
+            cout[u] = (uint32_t)(4096 * q + 16 * (16 * ig + (lane & 15)));
+        }
+        auto convert_unit = [&](int u, uint32_t src, uint32_t dst) __attribute__((always_inline)) {
+            const s16x4 v = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4 *)(uintptr_t)(src + cin[u]));
+            const uint2 w = __builtin_bit_cast(uint2, v);
+            uint32_t o0, o1, o2, o3;
+            f16_pairs(w.x, o0, o1);
+            f16_pairs(w.y, o2, o3);
+            *(lds_u4 *)(uintptr_t)(dst + cout[u]) = (u32x4){o0, o1, o2, o3};
+        };
+        static_assert(G::NCONV == NKS, "one conversion unit per K-step");
+        // this lane's unit of a staged fragment: sample group 2 KSTEP + lane / 32, input
+        // 32 R + lane % 32
+        const uint32_t lf = (uint32_t)(4096 * (lane >> 5) + 16 * (lane & 31));
+
+        wait_vm<(RING - 2) * DPW>();
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < G::NCONV; ++u) convert_unit(u, lds0, fb0);
+        int slot = 0, fb = 0;
+        int ready = 0;
+        while (cc.valid) {
+            // the copy of the next block (own, then everyone's) and the conversion of this
+            // one are complete; the raw slot of the previous block and the other operand
+            // buffer are free
+            if (ready == 0) wait_vm<(RING - 3) * DPW>();
+            else --ready;
+            __syncthreads();
+            issue(dc, slot == 0 ? RING - 1 : slot - 1);
+            dc.next(p);
+
+            // multiply this block, converting one unit of the next after each K-step so that
+            // the conversion overlaps the matrix cores
+            const uint32_t lvf = fb0 + fb * G::FBUF + lf;
+            const uint32_t csrc = lds0 + (slot == RING - 1 ? 0 : slot + 1) * G::BLK, cdst = fb0 + (fb ^ 1) * G::FBUF;
+            static_for<NKS>([&](auto K) __attribute__((always_inline)) {
+                kstep_staged<ACC, W, decltype(K)::value>(lvf, acc);
+                convert_unit(decltype(K)::value, csrc, cdst);
+            });
+            slot = slot == RING - 1 ? 0 : slot + 1;
+            fb ^= 1;
+
+            if (++cc.blk == cc.nblk) {
+                wait_vm<0>();
+                ready = RING - 2;
+                finish_item(cc);
+            }
         }
     }
     // no copy into LDS may outlive the workgroup
@@ -494,8 +721,8 @@ template <int ACC>
 int launch_chan_acc(const XJob &job, hipStream_t stream)
 {
     auto k = xeng_chan_kernel<ACC>;
-    if (int e = allow_lds_chan(k, CLDS)) return e;
-    hipLaunchKernelGGL(k, dim3((unsigned)job.grid), dim3(CT), CLDS, stream, job);
+    if (int e = allow_lds_chan(k, Geom<ACC>::LDS)) return e;
+    hipLaunchKernelGGL(k, dim3((unsigned)job.grid), dim3(CT), Geom<ACC>::LDS, stream, job);
     return (int)hipGetLastError();
 }
 

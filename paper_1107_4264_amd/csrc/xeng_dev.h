@@ -110,12 +110,29 @@ __device__ __forceinline__ void static_for(F &&f)
         std::make_integer_sequence<int, N>{});
 }
 
+// Lanes 2k and 2k+1 exchange values (quad_perm 1,0,3,2).
+__device__ __forceinline__ int swap_pair_lanes(int v) { return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false); }
+
+// The value lane l sends in a pair exchange where even lanes send a1 and odd lanes a0, i.e.
+// odd ? a0 : a1.  The choice is one bitfield-insert instruction on an all-ones mask of the
+// odd lanes, written as (non-volatile) assembly: the compiler must not see it as a choice on
+// the lane parity, or it may simplify the operand of the cross-lane move under the parity
+// of the receiving lane, which is wrong for the sending one.
+__device__ __forceinline__ int odd_lane_mask(int lane) { return -(lane & 1); }
+__device__ __forceinline__ int pair_send(int a0, int a1, int odd_mask)
+{
+    int r;
+    asm("v_bfi_b32 %0, %1, %2, %3" : "=v"(r) : "v"(odd_mask), "v"(a0), "v"(a1));
+    return r;
+}
+__device__ __forceinline__ float pair_send(float a0, float a1, int odd_mask)
+{
+    return __builtin_bit_cast(float, pair_send(__builtin_bit_cast(int, a0), __builtin_bit_cast(int, a1), odd_mask));
+}
 __device__ __forceinline__ float swap_pair_lanes(float v)
 {
-    // lanes 2k and 2k+1 exchange values (quad_perm 1,0,3,2)
-    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0xB1, 0xF, 0xF, false));
+    return __builtin_bit_cast(float, swap_pair_lanes(__builtin_bit_cast(int, v)));
 }
-__device__ __forceinline__ int swap_pair_lanes(int v) { return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false); }
 
 }  // namespace dev
 }  // namespace xc

@@ -381,6 +381,7 @@ __device__ __forceinline__ void store_tile(const XJob &p, int f, int row0, int c
         // rows p = 0, 1 of one station s1.  After one exchange each lane stores 16 bytes:
         // the even lane the slots (0,0), (0,1), the odd lane the slots (1,0), (1,1).
         const bool odd = lane & 1;
+        const int om = odd_lane_mask(lane);
 #pragma unroll
         for (int a = 0; a < NB; ++a)
 #pragma unroll
@@ -394,8 +395,8 @@ __device__ __forceinline__ void store_tile(const XJob &p, int f, int row0, int c
                     const int s1 = i >> 1;
                     const val_t r0 = (val_t)re[a][b][k], r1 = (val_t)re[a][b][k + 1];
                     const val_t m0 = (val_t)im[a][b][k], m1 = (val_t)im[a][b][k + 1];
-                    const val_t xr = swap_pair_lanes(odd ? r0 : r1);
-                    const val_t xm = swap_pair_lanes(odd ? m0 : m1);
+                    const val_t xr = swap_pair_lanes(pair_send(r0, r1, om));
+                    const val_t xm = swap_pair_lanes(pair_send(m0, m1, om));
                     if (i >= p.nin || j >= p.nin || s1 < s2) continue;
                     const int64_t o = ((int64_t)f * nbl + (int64_t)s1 * (s1 + 1) / 2 + s2) * 8 + (odd ? 4 : 0);
                     if constexpr (ACC == ACC_I8) {

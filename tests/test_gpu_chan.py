@@ -60,17 +60,22 @@ def test_chan_extreme_values(oracle_mod, acc):
     _check(got, oracle_mod.xcorr(x, ns, npol), f"chan-extreme/{acc}")
 
 
+# channels sampled from a walk over 700 channels: first, second and third items of
+# workgroups, and the last channel
+WALK_CHANS = [0, 1, 8, 9, 16, 17, 24, 31, 254, 255, 256, 257, 264, 280, 511, 512, 699]
+
+
 @pytest.mark.parametrize("acc", ACCS)
-def test_chan_many_channels_per_workgroup(oracle_mod, acc):
+@pytest.mark.parametrize("npol", [2, 1])
+def test_chan_many_channels_per_workgroup(oracle_mod, acc, npol):
     """More channels than compute units: each workgroup walks several channels and copies
     the next channel's first blocks while finishing the current one."""
-    ns, npol, F, T = 128, 2, 700, 150
+    ns, F, T = 256 // npol, 700, 150
     x = synth.voltages_np(synth.SEED_BASE + 42, T, F, ns * npol, ("gauss", 20.0, 127))
-    chans = [0, 1, 255, 256, 257, 511, 512, 699]
-    say("chan walk", acc, "F", F)
+    say("chan walk", acc, "npol", npol, "F", F)
     got, _ = run_xeng(x, ns, npol, "ci8", acc, tile=256)
-    want = oracle_mod.xcorr(x, ns, npol, chans=chans)
-    _check(got[chans], want, f"chan-walk/{acc}")
+    want = oracle_mod.xcorr(x, ns, npol, chans=WALK_CHANS)
+    _check(got[WALK_CHANS], want, f"chan-walk/{acc}/{npol}")
 
 
 def test_chan_windows_f16(oracle_mod):
