@@ -34,8 +34,10 @@ HBM_PEAK_GBPS = 8000.0
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--ramp-seconds", type=float, default=0.3,
+                    help="untimed run time per path before the warmup steps, so that clocks have settled")
     ap.add_argument("--paths", default="f32,f16,i8")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
@@ -84,6 +86,12 @@ def main():
         c = X.Correlator(ns, npol, F, T, "ci8", p, max_abs=max_abs, tile=tile)
         plan = X.xcorr_plan(ns, npol, F, T, X.IN_CI8, X.ACC_NAMES[p], max_abs, tile)
         out = c.empty_out(dev)
+        # clocks ramp up under load: run the path untimed for a while, then the warmup steps
+        t_ramp = time.perf_counter()
+        while time.perf_counter() - t_ramp < args.ramp_seconds:
+            for _ in range(10):
+                c.run(x, out)
+            torch.cuda.synchronize()
         for _ in range(args.warmup):
             c.run(x, out)
         torch.cuda.synchronize()
@@ -154,7 +162,7 @@ def main():
             "peak": PEAK_TFLOPS[head],
             "unit": "TFLOP/s",
             "frac": round(hr["frac_of_peak"], 4),
-            "traffic": None,
+            "traffic": hbm_traffic(head, plan),
         },
         "paths": {k: {kk: (round(vv, 5) if isinstance(vv, float) else vv) for kk, vv in r.items()}
                   for k, r in results.items()},
@@ -166,6 +174,31 @@ def main():
     if not args.no_cpu_baseline and not args.only:
         line["cpu_baseline"], line["parity"] = cpu_baseline(args, x, outs[head], ns, npol, F, T, seed)
     print(json.dumps(line), flush=True)
+
+
+TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                            "xeng_chan_256in_1024ch_1000t_hbm_traffic.json")
+
+
+def hbm_traffic(path, plan):
+    """HBM bytes per launch of the path's kernel, from the counter runs recorded in
+    TRAFFIC_FILE (FETCH_SIZE and WRITE_SIZE, scaled by their calibration against kernels of
+    known traffic), if they were taken on the current kernel source; otherwise None."""
+    import hashlib
+
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as fh:
+        rec = json.load(fh)
+    here = os.path.dirname(os.path.abspath(__file__))
+    h = hashlib.sha256()
+    for f in rec["sources"]:
+        with open(os.path.join(here, f), "rb") as fh:
+            h.update(fh.read())
+    entry = rec["paths"].get(path)
+    if h.hexdigest() != rec["sources_sha256"] or entry is None or plan["tile"] != rec["tile"]:
+        return None
+    return int(entry["fetch_kib"] * 1024 * rec["fetch_factor"] + entry["write_kib"] * 1024 * rec["write_factor"])
 
 
 def cpu_baseline(args, x, out_head, ns, npol, F, T, seed):
