@@ -22,10 +22,19 @@ import sys
 import time
 
 METRIC = "X-engine TFLOPS (8/CMAC) & % of peak: FP32 CMAC vs int8/FP16 MFMA, N=256 inputs"
-WORKLOAD = {
-    "name": "256 inputs (128 stations x 2 pol), 1024 channels, 1000 samples, ci8 gaussian sigma=3 clipped to +-127",
-    "nstation": 128, "npol": 2, "nchan": 1024, "ntime": 1000,
-    "dist": ("gauss", 3.0, 127), "seed_index": 1,
+# The headline workload and the compute-bound 4-bit one.  A step is one xcorr_run over the
+# whole input, resident in HBM.
+WORKLOADS = {
+    "n256-ci8": {
+        "name": "256 inputs (128 stations x 2 pol), 1024 channels, 1000 samples, ci8 gaussian sigma=3 clipped to +-127",
+        "nstation": 128, "npol": 2, "nchan": 1024, "ntime": 1000, "in": "ci8",
+        "dist": ("gauss", 3.0, 127), "seed_index": 1, "paths": "f32,f16,i8", "head": "f16",
+    },
+    "n1024-ci4": {
+        "name": "1024 inputs (512 stations x 2 pol), 256 channels, 4096 samples, ci4 uniform [-8, 7]",
+        "nstation": 512, "npol": 2, "nchan": 256, "ntime": 4096, "in": "ci4",
+        "dist": ("uniform", -8, 7), "seed_index": 2, "paths": "i8,f8", "head": "i8",
+    },
 }
 PEAK_TFLOPS = {"f16": 2500.0, "i8": 5000.0, "f8": 5000.0, "f32": 157.3}
 HBM_PEAK_GBPS = 8000.0
@@ -38,7 +47,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--ramp-seconds", type=float, default=0.3,
                     help="untimed run time per path before the warmup steps, so that clocks have settled")
-    ap.add_argument("--paths", default="f32,f16,i8")
+    ap.add_argument("--workload", default="n256-ci8", choices=sorted(WORKLOADS))
+    ap.add_argument("--paths", default=None, help="comma-separated paths (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
     ap.add_argument("--only", default=None, help="time only this path (for profiling runs)")
@@ -63,19 +73,24 @@ def main():
     from paper_1107_4264_amd import xcorr as X
 
     dev = torch.device("cuda:0")
-    w = WORKLOAD
+    w = WORKLOADS[args.workload]
     ns, npol, F, T = w["nstation"], w["npol"], w["nchan"], w["ntime"]
     nin = ns * npol
     seed = synth.SEED_BASE + w["seed_index"]
-    print(f"[bench] generating input {T}x{F}x{nin} ci8 on device", file=sys.stderr, flush=True)
+    fmt = w["in"]
+    in_enum = X.IN_CI8 if fmt == "ci8" else X.IN_CI4
+    print(f"[bench] generating input {T}x{F}x{nin} {fmt} on device", file=sys.stderr, flush=True)
     x = synth.voltages_torch(seed, T, F, nin, w["dist"], dev)
     torch.cuda.synchronize()
     max_abs = int(x.abs().max().item())
     # the device generator reproduces the host definition (checked on one channel)
     chk = synth.voltages_np(seed, T, F, nin, w["dist"], chans=[F // 3])
     assert np.array_equal(x[:, F // 3: F // 3 + 1].cpu().numpy(), chk), "device generator mismatch"
+    if fmt == "ci4":
+        x = synth.pack_ci4_torch(x)
+        torch.cuda.synchronize()
 
-    paths = [p for p in args.paths.split(",") if p]
+    paths = [p for p in (args.paths or w["paths"]).split(",") if p]
     if args.only:
         paths = [args.only]
     results = {}
@@ -83,8 +98,8 @@ def main():
     stream = torch.cuda.current_stream()
     for p in paths:
         tile = args.tile if p != "f32" else 0
-        c = X.Correlator(ns, npol, F, T, "ci8", p, max_abs=max_abs, tile=tile)
-        plan = X.xcorr_plan(ns, npol, F, T, X.IN_CI8, X.ACC_NAMES[p], max_abs, tile)
+        c = X.Correlator(ns, npol, F, T, fmt, p, max_abs=max_abs, tile=tile)
+        plan = X.xcorr_plan(ns, npol, F, T, in_enum, X.ACC_NAMES[p], max_abs, tile)
         out = c.empty_out(dev)
         # clocks ramp up under load: run the path untimed for a while, then the warmup steps
         t_ramp = time.perf_counter()
@@ -138,9 +153,9 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    head = "f16" if "f16" in results else paths[0]
+    head = w["head"] if w["head"] in results else paths[0]
     hr = results[head]
-    plan = X.xcorr_plan(ns, npol, F, T, X.IN_CI8, X.ACC_NAMES[head], max_abs, args.tile if head != "f32" else 0)
+    plan = X.xcorr_plan(ns, npol, F, T, in_enum, X.ACC_NAMES[head], max_abs, args.tile if head != "f32" else 0)
     line = {
         "metric": METRIC,
         "value": round(hr["tflops"], 3),
@@ -155,14 +170,15 @@ def main():
         "dtype": {"f16": "f16", "i8": "i8", "f32": "f32", "f8": "fp8"}[head],
         "data": "synthetic",
         "config": {"workload": w["name"], "nstation": ns, "npol": npol, "nchan": F, "ntime": T,
-                   "in_dtype": "ci8", "max_abs": max_abs, "path": f"{head} mfma" if head != "f32" else "f32 cmac"},
+                   "in_dtype": fmt, "max_abs": max_abs, "tile": plan["tile"],
+                   "path": f"{head} mfma" if head != "f32" else "f32 cmac"},
         "roofline": {
             "bound": "mfma" if head != "f32" else "alu",
             "achieved": round(hr["tflops"], 3),
             "peak": PEAK_TFLOPS[head],
             "unit": "TFLOP/s",
             "frac": round(hr["frac_of_peak"], 4),
-            "traffic": hbm_traffic(head, plan),
+            "traffic": hbm_traffic(head, plan) if args.workload == "n256-ci8" else None,
         },
         "paths": {k: {kk: (round(vv, 5) if isinstance(vv, float) else vv) for kk, vv in r.items()}
                   for k, r in results.items()},
@@ -172,7 +188,7 @@ def main():
         line["speedup_vs_f32_cmac"] = round(results["f32"]["ms_per_step"] / hr["ms_per_step"], 2)
 
     if not args.no_cpu_baseline and not args.only:
-        line["cpu_baseline"], line["parity"] = cpu_baseline(args, x, outs[head], ns, npol, F, T, seed)
+        line["cpu_baseline"], line["parity"] = cpu_baseline(args, w, outs[head], ns, npol, F, T, seed)
     print(json.dumps(line), flush=True)
 
 
@@ -201,7 +217,7 @@ def hbm_traffic(path, plan):
     return int(entry["fetch_kib"] * 1024 * rec["fetch_factor"] + entry["write_kib"] * 1024 * rec["write_factor"])
 
 
-def cpu_baseline(args, x, out_head, ns, npol, F, T, seed):
+def cpu_baseline(args, w, out_head, ns, npol, F, T, seed):
     """The oracle on a bounded sample of channels of the same workload, on the host cores;
     the sampled channels are also compared with the GPU output."""
     import numpy as np
@@ -210,21 +226,27 @@ def cpu_baseline(args, x, out_head, ns, npol, F, T, seed):
     from paper_1107_4264_amd import synth
 
     oracle.build()
-    w = WORKLOAD
     nin = ns * npol
+    ci4 = w["in"] == "ci4"
+
+    def host_input(chans):
+        v = synth.voltages_np(seed, T, F, nin, w["dist"], chans=chans)
+        return synth.pack_ci4(v) if ci4 else v
+
+    ofmt = oracle.CI4 if ci4 else oracle.CI8
     cores = oracle.num_threads()
     # size the sample: time one channel first
     rng = np.random.default_rng(0)
     first = [int(rng.integers(F))]
-    xs = synth.voltages_np(seed, T, F, nin, w["dist"], chans=first)
+    xs = host_input(first)
     t0 = time.perf_counter()
-    oracle.xcorr(xs, ns, npol, chans=[0])
+    oracle.xcorr(xs, ns, npol, fmt=ofmt, chans=[0])
     one = time.perf_counter() - t0
     nsel = min(F, max(1, cores * max(1, int(args.cpu_seconds / max(one, 1e-6)))))
     chans = np.sort(rng.choice(F, size=nsel, replace=False))
-    xs = synth.voltages_np(seed, T, F, nin, w["dist"], chans=chans)
+    xs = host_input(chans)
     t0 = time.perf_counter()
-    want = oracle.xcorr(xs, ns, npol, chans=np.arange(nsel))
+    want = oracle.xcorr(xs, ns, npol, fmt=ofmt, chans=np.arange(nsel))
     dt = time.perf_counter() - t0
     useful = nin * (nin + 1) // 2 * nsel * T
     got = out_head[chans.tolist()].cpu().numpy()
