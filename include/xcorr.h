@@ -131,6 +131,26 @@ int xcorr_set_tile(xcorr_handle_t *h, int tile);
 /* The kernel shape the handle runs (64, 128 or 256), or an error code. */
 int xcorr_get_tile(const xcorr_handle_t *h);
 
+/* Autotuner (the tile-size search of Sec. 4.2 / 6, done on the device): run every kernel
+ * shape the job allows `reps` times (after one warm-up) on `in` / `out` on `stream`, timed
+ * with HIP events, keep the fastest on the handle and record it in the process-wide tuning
+ * cache under the job's shape (nstation, npol, nchan, ntime, formats, max_abs).  Handles
+ * created or re-planned later with a cached shape start with the tuned tile.  Returns the
+ * chosen tile (> 0) or an error code.  Synchronises the host with `stream`; `out` holds the
+ * visibilities of `in` afterwards (every shape gives the same bits).  reps in 1..1000. */
+int xcorr_autotune(xcorr_handle_t *h, const void *in, void *out, hipStream_t stream, int reps);
+
+/* Tile cached for a job shape (max_abs 0: the default bound), 0 if none, or an error code. */
+int xcorr_autotune_lookup(int nstation, int npol, int nchan, int ntime, xcorr_in_dtype in_dtype,
+                          xcorr_acc_dtype acc_dtype, int max_abs);
+
+/* Keep the tuning cache in a text file (one JSON object per line: the shape, "tile" and the
+ * measured "us"); load merges into the cache.  Return the number of entries, or
+ * XCORR_ERR_INVALID_ARG on an I/O or format error. */
+int xcorr_autotune_save(const char *path);
+int xcorr_autotune_load(const char *path);
+void xcorr_autotune_clear(void);
+
 /* Compute the visibilities of `in` (device, xcorr_in_bytes) into `out` (device,
  * xcorr_out_bytes) on `stream` (0 = the null stream). */
 int xcorr_run(xcorr_handle_t *h, const void *in, void *out, hipStream_t stream);
@@ -222,6 +242,18 @@ size_t xcorr_stream_chunk_bytes(const xcorr_stream_t *s);
 size_t xcorr_stream_out_bytes(const xcorr_stream_t *s);
 int xcorr_stream_out_type(const xcorr_stream_t *s);
 void xcorr_stream_destroy(xcorr_stream_t *s);
+
+/* Record a whole integration of nchunk chunks (begin, one push per host_chunks[c], end)
+ * into a HIP graph, once, and return it instantiated in *exec.  Every launch of the graph
+ * (xcorr_graph_launch, or hipGraphLaunch) zeroes `out` and integrates the chunks as they
+ * are in host memory at that time, with the same copy/compute overlap; the host pointers
+ * and `out` are baked in and must stay valid while the graph is used.  Launches of one
+ * graph, and runs of its stream object, must not overlap.  Nothing is enqueued by the
+ * capture itself.  On failure *exec is NULL and an error code is returned. */
+int xcorr_stream_capture(xcorr_stream_t *s, int nchunk, const void *const *host_chunks, void *out,
+                         hipGraphExec_t *exec);
+int xcorr_graph_launch(hipGraphExec_t exec, hipStream_t stream);
+void xcorr_graph_destroy(hipGraphExec_t exec);
 
 /* ------------------------------------------------------------------ host-only planning */
 

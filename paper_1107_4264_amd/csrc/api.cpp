@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "plan.h"
+#include "tune.h"
 #include "xcorr.h"
 #include "xeng.h"
 
@@ -124,6 +125,24 @@ int enqueue_job(const Plan &pl, const void *in, void *out, hipStream_t stream)
     return XCORR_OK;
 }
 
+TuneKey key_of(const Plan &p)
+{
+    return TuneKey{p.nstation, p.npol, p.nchan, p.ntime, p.in_fmt, p.acc, p.max_abs};
+}
+
+// Switch a plan to the tile the autotuner recorded for its shape, if any (and still valid).
+void apply_tuned(Plan &p)
+{
+    const int t = tune_lookup(key_of(p));
+    if (t == 0 || t == p.tile) return;
+    Plan q;
+    std::string err;
+    if (make_plan(p.nstation, p.npol, p.nchan, p.ntime, p.in_fmt, p.acc, p.max_abs, t, &q, &err) == XCORR_OK) {
+        q.max_abs = p.max_abs;
+        p = q;
+    }
+}
+
 }  // namespace
 
 struct xcorr_handle {
@@ -193,6 +212,7 @@ xcorr_handle_t *xcorr_create(int nstation, int npol, int nchan, int ntime, xcorr
         return nullptr;
     }
     if (acc_dtype == XCORR_ACC_F8E4M3_MMA_F32 && in_dtype == XCORR_IN_CI8) p.max_abs = 128;
+    apply_tuned(p);
     int dev = 0;
     hipError_t he = hipGetDevice(&dev);
     if (he != hipSuccess) {
@@ -218,9 +238,92 @@ int xcorr_set_max_abs(xcorr_handle_t *h, int max_abs)
     const Plan &o = h->plan;
     const int rc = make_plan(o.nstation, o.npol, o.nchan, o.ntime, o.in_fmt, o.acc, max_abs, o.tile, &p, &err);
     if (rc) return fail(rc, err);
+    apply_tuned(p);
     h->plan = p;
     return XCORR_OK;
 }
+
+int xcorr_autotune(xcorr_handle_t *h, const void *in, void *out, hipStream_t stream, int reps)
+{
+    if (!h) return fail(XCORR_ERR_INVALID_ARG, "null handle");
+    if (!out || (!in && h->plan.ntime > 0)) return fail(XCORR_ERR_INVALID_ARG, "null input or output");
+    if (reps < 1 || reps > 1000) return fail(XCORR_ERR_INVALID_ARG, "reps must be in 1..1000");
+    const Plan &o = h->plan;
+    std::vector<Plan> cand;
+    for (int t : {CHAN_TILE, 128, 64}) {
+        Plan q;
+        std::string err;
+        if (make_plan(o.nstation, o.npol, o.nchan, o.ntime, o.in_fmt, o.acc, o.max_abs, t, &q, &err) == XCORR_OK) {
+            q.max_abs = o.max_abs;
+            cand.push_back(q);
+        }
+    }
+    if (cand.empty()) return fail(XCORR_ERR_UNSUPPORTED, "no kernel shape accepts this job");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t he;
+    if ((he = hipEventCreate(&e0)) != hipSuccess || (he = hipEventCreate(&e1)) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return hip_fail((int)he, "autotune events");
+    }
+    int best = -1;
+    double best_us = 0.0;
+    int rc = XCORR_OK;
+    for (size_t c = 0; c < cand.size() && rc == XCORR_OK; ++c) {
+        rc = enqueue_job(cand[c], in, out, stream);  // warm-up
+        if (rc) break;
+        if ((he = hipEventRecord(e0, stream)) != hipSuccess) {
+            rc = hip_fail((int)he, "autotune event");
+            break;
+        }
+        for (int r = 0; r < reps && rc == XCORR_OK; ++r) rc = enqueue_job(cand[c], in, out, stream);
+        if (rc) break;
+        float ms = 0.0f;
+        if ((he = hipEventRecord(e1, stream)) != hipSuccess || (he = hipEventSynchronize(e1)) != hipSuccess ||
+            (he = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) {
+            rc = hip_fail((int)he, "autotune timing");
+            break;
+        }
+        const double us = 1000.0 * ms / reps;
+        if (best < 0 || us < best_us) {
+            best = (int)c;
+            best_us = us;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    h->plan = cand[best];
+    tune_record(key_of(h->plan), h->plan.tile, best_us);
+    return h->plan.tile;
+}
+
+int xcorr_autotune_lookup(int nstation, int npol, int nchan, int ntime, xcorr_in_dtype in_dtype,
+                          xcorr_acc_dtype acc_dtype, int max_abs)
+{
+    Plan p;
+    std::string err;
+    const int rc = make_plan(nstation, npol, nchan, ntime, (int)in_dtype, (int)acc_dtype, max_abs, 0, &p, &err);
+    if (rc) return fail(rc, err);
+    return tune_lookup(key_of(p));
+}
+
+int xcorr_autotune_save(const char *path)
+{
+    if (!path) return fail(XCORR_ERR_INVALID_ARG, "null path");
+    std::string err;
+    const int n = tune_save(path, &err);
+    return n < 0 ? fail(XCORR_ERR_INVALID_ARG, err) : n;
+}
+
+int xcorr_autotune_load(const char *path)
+{
+    if (!path) return fail(XCORR_ERR_INVALID_ARG, "null path");
+    std::string err;
+    const int n = tune_load(path, &err);
+    return n < 0 ? fail(XCORR_ERR_INVALID_ARG, err) : n;
+}
+
+void xcorr_autotune_clear(void) { tune_clear(); }
 
 int xcorr_set_tile(xcorr_handle_t *h, int tile)
 {
@@ -652,5 +755,56 @@ int xcorr_stream_out_type(const xcorr_stream_t *s)
 }
 
 void xcorr_stream_destroy(xcorr_stream_t *s) { stream_free(s); }
+
+int xcorr_stream_capture(xcorr_stream_t *s, int nchunk, const void *const *host_chunks, void *out,
+                         hipGraphExec_t *exec)
+{
+    if (!s || !exec || !out || nchunk < 1 || !host_chunks)
+        return fail(XCORR_ERR_INVALID_ARG, "null argument or nchunk < 1");
+    for (int c = 0; c < nchunk; ++c)
+        if (!host_chunks[c]) return fail(XCORR_ERR_INVALID_ARG, "null chunk");
+    *exec = nullptr;
+    hipStream_t cs = nullptr;
+    hipError_t he = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (he != hipSuccess) return hip_fail((int)he, "capture stream");
+    // relaxed mode: the first launch of a kernel may set its LDS limit while capturing
+    he = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
+    if (he != hipSuccess) {
+        (void)hipStreamDestroy(cs);
+        return hip_fail((int)he, "begin capture");
+    }
+    int rc = xcorr_stream_begin(s, out, cs);
+    for (int c = 0; c < nchunk && rc == XCORR_OK; ++c) rc = xcorr_stream_push(s, host_chunks[c], cs);
+    if (rc == XCORR_OK) {
+        const int64_t n = xcorr_stream_end(s, cs);
+        if (n < 0) rc = (int)n;
+    } else {
+        s->out = nullptr;
+    }
+    // end the capture in every case; a failure above keeps its own message
+    hipGraph_t g = nullptr;
+    he = hipStreamEndCapture(cs, &g);
+    if (rc == XCORR_OK && he != hipSuccess) rc = hip_fail((int)he, "end capture");
+    if (rc == XCORR_OK) {
+        he = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
+        if (he != hipSuccess) rc = hip_fail((int)he, "instantiate graph");
+    }
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipStreamDestroy(cs);
+    if (rc != XCORR_OK) *exec = nullptr;
+    return rc;
+}
+
+int xcorr_graph_launch(hipGraphExec_t exec, hipStream_t stream)
+{
+    if (!exec) return fail(XCORR_ERR_INVALID_ARG, "null graph");
+    const hipError_t he = hipGraphLaunch(exec, stream);
+    return he == hipSuccess ? XCORR_OK : hip_fail((int)he, "graph launch");
+}
+
+void xcorr_graph_destroy(hipGraphExec_t exec)
+{
+    if (exec) (void)hipGraphExecDestroy(exec);
+}
 
 }  // extern "C"

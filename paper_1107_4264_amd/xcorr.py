@@ -67,6 +67,11 @@ def _load():
         "xcorr_set_max_abs": (c_int, [c_vp, c_int]),
         "xcorr_set_tile": (c_int, [c_vp, c_int]),
         "xcorr_get_tile": (c_int, [c_vp]),
+        "xcorr_autotune": (c_int, [c_vp, c_vp, c_vp, c_vp, c_int]),
+        "xcorr_autotune_lookup": (c_int, [c_int, c_int, c_int, c_int, c_int, c_int, c_int]),
+        "xcorr_autotune_save": (c_int, [ctypes.c_char_p]),
+        "xcorr_autotune_load": (c_int, [ctypes.c_char_p]),
+        "xcorr_autotune_clear": (None, []),
         "xcorr_run": (c_int, [c_vp, c_vp, c_vp, c_vp]),
         "xcorr_destroy": (None, [c_vp]),
         "xcorr_in_bytes": (c_sz, [c_vp]),
@@ -93,6 +98,9 @@ def _load():
         "xcorr_stream_out_bytes": (c_sz, [c_vp]),
         "xcorr_stream_out_type": (c_int, [c_vp]),
         "xcorr_stream_destroy": (None, [c_vp]),
+        "xcorr_stream_capture": (c_int, [c_vp, c_int, c_vp, c_vp, ctypes.POINTER(c_vp)]),
+        "xcorr_graph_launch": (c_int, [c_vp, c_vp]),
+        "xcorr_graph_destroy": (None, [c_vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -144,6 +152,26 @@ def xcorr_set_tile(h, tile):
 
 def xcorr_get_tile(h):
     return _check(_lib.xcorr_get_tile(h))
+
+
+def xcorr_autotune(h, in_ptr, out_ptr, stream_ptr, reps=3):
+    return _check(_lib.xcorr_autotune(h, in_ptr, out_ptr, stream_ptr, reps))
+
+
+def xcorr_autotune_lookup(nstation, npol, nchan, ntime, in_dtype, acc_dtype, max_abs=0):
+    return _check(_lib.xcorr_autotune_lookup(nstation, npol, nchan, ntime, in_dtype, acc_dtype, max_abs))
+
+
+def xcorr_autotune_save(path):
+    return _check(_lib.xcorr_autotune_save(os.fsencode(path)))
+
+
+def xcorr_autotune_load(path):
+    return _check(_lib.xcorr_autotune_load(os.fsencode(path)))
+
+
+def xcorr_autotune_clear():
+    _lib.xcorr_autotune_clear()
 
 
 def xcorr_run(h, in_ptr, out_ptr, stream_ptr):
@@ -266,6 +294,23 @@ def xcorr_stream_destroy(s):
     _lib.xcorr_stream_destroy(s)
 
 
+def xcorr_stream_capture(s, host_ptrs, out_ptr):
+    """Instantiated graph (as an integer handle) of a whole integration over host_ptrs."""
+    n = len(host_ptrs)
+    arr = (ctypes.c_void_p * n)(*host_ptrs)
+    ex = ctypes.c_void_p()
+    _check(_lib.xcorr_stream_capture(s, n, ctypes.cast(arr, ctypes.c_void_p), out_ptr, ctypes.byref(ex)))
+    return ex.value
+
+
+def xcorr_graph_launch(exec_handle, stream_ptr):
+    return _check(_lib.xcorr_graph_launch(ctypes.c_void_p(exec_handle), stream_ptr))
+
+
+def xcorr_graph_destroy(exec_handle):
+    _lib.xcorr_graph_destroy(ctypes.c_void_p(exec_handle))
+
+
 # ------------------------------------------------------------------ torch convenience
 
 def out_torch_dtype(out_type):
@@ -326,6 +371,13 @@ class Correlator:
         import torch
 
         return torch.empty(self.out_shape(), dtype=out_torch_dtype(self.out_type), device=device)
+
+    def autotune(self, x, out=None, reps=3, stream=None):
+        """Time every allowed kernel shape on x and keep the fastest; returns the tile."""
+        if out is None:
+            out = self.empty_out(x.device)
+        return xcorr_autotune(self.h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                              _stream_ptr(stream), reps)
 
     def run(self, x, out=None, stream=None):
         """x: device tensor holding xcorr_in_bytes bytes of samples; returns the output."""
@@ -436,3 +488,39 @@ class Stream:
 
     def end(self, stream=None):
         return xcorr_stream_end(self.s, _stream_ptr(stream))
+
+    def capture(self, chunks, out=None):
+        """A HIP graph of a whole integration over these host chunks into `out`: each
+        launch zeroes `out` and integrates the chunks' current contents."""
+        out = self.empty_out() if out is None else out
+        if out.numel() * out.element_size() != xcorr_stream_out_bytes(self.s):
+            raise ValueError("totals buffer does not match the plan")
+        for ch in chunks:
+            if ch.is_cuda or ch.numel() * ch.element_size() != xcorr_stream_chunk_bytes(self.s):
+                raise ValueError("chunks must be host tensors of xcorr_stream_chunk_bytes")
+        ex = xcorr_stream_capture(self.s, [ch.data_ptr() for ch in chunks], ctypes.c_void_p(out.data_ptr()))
+        return Graph(ex, out, list(chunks))
+
+
+class Graph:
+    """An instantiated HIP graph of the library (keeps its buffers alive)."""
+
+    def __init__(self, exec_handle, out, keep):
+        self.exec = exec_handle
+        self.out = out
+        self._keep = keep
+
+    def launch(self, stream=None):
+        xcorr_graph_launch(self.exec, _stream_ptr(stream))
+        return self.out
+
+    def close(self):
+        if self.exec:
+            xcorr_graph_destroy(self.exec)
+            self.exec = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

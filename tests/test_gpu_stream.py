@@ -61,3 +61,43 @@ def test_stream_windows_within_chunk(oracle_mod):
     torch.cuda.synchronize()
     assert np.array_equal(as_exact_int(out.cpu().numpy()), want)
     st.close()
+
+
+@pytest.mark.parametrize("acc", ["i8", "f16"])
+def test_stream_graph_replays(oracle_mod, acc):
+    """A whole integration captured once as a HIP graph: each replay re-reads the pinned
+    chunks and recomputes the totals; replays are interleaved with eager work and host
+    synchronisation, and every replay is checked (the zero fill is a kernel, not a memset
+    node)."""
+    import torch
+
+    from paper_1107_4264_amd import xcorr as X
+
+    dev = device()
+    ns, npol, F, chunk, nchunk = 128, 2, 3, 64, 4
+    st = X.Stream(ns, npol, F, chunk, "ci8", acc)
+    chunks = [torch.empty((chunk, F, ns * npol, 2), dtype=torch.int8).pin_memory() for _ in range(nchunk)]
+    out = st.empty_out(dev)
+    g = st.capture(chunks, out)
+    for rep in range(3):
+        x = synth.voltages_np(5150 + rep, chunk * nchunk, F, ns * npol, ("gauss", 40.0, 127))
+        for c in range(nchunk):
+            chunks[c].copy_(torch.from_numpy(np.ascontiguousarray(x[c * chunk:(c + 1) * chunk])))
+        # some eager work on the device between replays
+        junk = torch.randn(1 << 20, device=dev)
+        junk.mul_(2.0)
+        torch.cuda.synchronize()
+        say("graph replay", acc, rep)
+        g.launch()
+        torch.cuda.synchronize()
+        assert np.array_equal(as_exact_int(out.cpu().numpy()), oracle_mod.xcorr(x, ns, npol)), rep
+    # the same stream object still runs eagerly afterwards
+    x = synth.voltages_np(5160, chunk * nchunk, F, ns * npol, ("gauss", 40.0, 127))
+    out2 = st.begin()
+    for c in range(nchunk):
+        st.push(torch.from_numpy(np.ascontiguousarray(x[c * chunk:(c + 1) * chunk])).pin_memory())
+    st.end()
+    torch.cuda.synchronize()
+    assert np.array_equal(as_exact_int(out2.cpu().numpy()), oracle_mod.xcorr(x, ns, npol))
+    g.close()
+    st.close()
