@@ -47,7 +47,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--ramp-seconds", type=float, default=0.3,
                     help="untimed run time per path before the warmup steps, so that clocks have settled")
-    ap.add_argument("--workload", default="n256-ci8", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="n256-ci8", choices=sorted(WORKLOADS) + ["batch64", "stream"])
     ap.add_argument("--paths", default=None, help="comma-separated paths (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
@@ -73,6 +73,10 @@ def main():
     from paper_1107_4264_amd import xcorr as X
 
     dev = torch.device("cuda:0")
+    if args.workload == "batch64":
+        return bench_batch(args, dev)
+    if args.workload == "stream":
+        return bench_stream(args, dev)
     w = WORKLOADS[args.workload]
     ns, npol, F, T = w["nstation"], w["npol"], w["nchan"], w["ntime"]
     nin = ns * npol
@@ -190,6 +194,214 @@ def main():
     if not args.no_cpu_baseline and not args.only:
         line["cpu_baseline"], line["parity"] = cpu_baseline(args, w, outs[head], ns, npol, F, T, seed)
     print(json.dumps(line), flush=True)
+
+
+BATCH = {
+    "name": "64 uneven jobs: inputs 2*U{24..288} (dual pol), 32..512 channels, 128..8192 samples, "
+            "ci8 gaussian sigma=8 clipped to +-127",
+    "seed_index": 3, "dist": ("gauss", 8.0, 127), "path": "i8",
+}
+
+
+def bench_batch(args, dev):
+    """All jobs in one persistent launch against one launch per job (each with its own
+    automatic kernel shape); value = useful TFLOPS of the persistent launch."""
+    import numpy as np
+    import torch
+
+    from paper_1107_4264_amd import synth
+    from paper_1107_4264_amd import xcorr as X
+
+    seed = synth.SEED_BASE + BATCH["seed_index"]
+    jobs = synth.draw_jobs(seed)
+    acc = BATCH["path"]
+    print(f"[bench] generating {len(jobs)} job inputs on device", file=sys.stderr, flush=True)
+    xs = [synth.voltages_torch(seed + 16 * (k + 1), j["ntime"], j["nchan"], j["nstation"] * j["npol"],
+                               BATCH["dist"], dev) for k, j in enumerate(jobs)]
+    torch.cuda.synchronize()
+    max_abs = max(int(x.abs().max().item()) for x in xs)
+    useful = sum((j["nstation"] * j["npol"]) * (j["nstation"] * j["npol"] + 1) // 2 * j["nchan"] * j["ntime"]
+                 for j in jobs)
+    in_bytes = sum(x.numel() for x in xs)
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        t_ramp = time.perf_counter()
+        while time.perf_counter() - t_ramp < args.ramp_seconds:
+            fn()
+            torch.cuda.synchronize()
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / args.steps
+
+    b = X.Batch(jobs, "ci8", acc, max_abs=max_abs)
+    outs_b = b.empty_outs(dev)
+    ms_batch = timed(lambda: b.run(xs, outs_b))
+    print(f"[bench] batch: {ms_batch:.3f} ms/step, {8.0 * useful / (ms_batch * 1e-3) / 1e12:.1f} TFLOPS",
+          file=sys.stderr, flush=True)
+    cs = [X.Correlator(j["nstation"], j["npol"], j["nchan"], j["ntime"], "ci8", acc, max_abs=max_abs) for j in jobs]
+    outs_j = [c.empty_out(dev) for c in cs]
+
+    def per_job():
+        for c, x, o in zip(cs, xs, outs_j):
+            c.run(x, o)
+
+    ms_jobs = timed(per_job)
+    print(f"[bench] per-job launches: {ms_jobs:.3f} ms/step", file=sys.stderr, flush=True)
+    same = all(torch.equal(a, bb) for a, bb in zip(outs_b, outs_j))
+    tiles = sorted({c.tile for c in cs})
+    tflops = 8.0 * useful / (ms_batch * 1e-3) / 1e12
+    line = {
+        "metric": METRIC, "value": round(tflops, 3), "unit": "TFLOPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_batch, 5), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "i8", "data": "synthetic",
+        "config": {"workload": BATCH["name"], "jobs": len(jobs), "useful_cmacs": useful, "in_bytes": in_bytes,
+                   "max_abs": max_abs, "path": "i8 mfma, one persistent launch"},
+        "roofline": {"bound": "mfma", "achieved": round(tflops, 3), "peak": PEAK_TFLOPS["i8"], "unit": "TFLOP/s",
+                     "frac": round(tflops / PEAK_TFLOPS["i8"], 4), "traffic": None},
+        "per_job_launches": {"ms_per_step": round(ms_jobs, 5), "tflops": round(8.0 * useful / (ms_jobs * 1e-3) / 1e12, 3),
+                             "tiles": tiles},
+        "batch_speedup_vs_per_job": round(ms_jobs / ms_batch, 3),
+        "parity": "persistent and per-job launches agree exactly" if same else "MISMATCH between launch modes",
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"], ok = batch_cpu_baseline(args, jobs, seed, outs_b)
+        line["parity"] += "; sampled channels bit-exact against the oracle" if ok else "; MISMATCH against the oracle"
+    print(json.dumps(line), flush=True)
+
+
+STREAM = {
+    "name": "streaming integration: 1024 inputs (512 stations x 2 pol), 512 channels, 16 chunks of 4096 samples "
+            "from a pool of 2 pinned host chunks, ci8 gaussian sigma=20 clipped to +-127",
+    "nstation": 512, "npol": 2, "nchan": 512, "chunk": 4096, "nchunk": 16, "pool": 2,
+    "dist": ("gauss", 20.0, 127), "seed_index": 4, "path": "i8",
+}
+
+
+def bench_stream(args, dev):
+    """End-to-end chunked integration from pinned host memory (copies overlapped with the
+    X-engine); a step is the whole integration, wall time includes the host-to-device copies."""
+    import numpy as np
+    import torch
+
+    from paper_1107_4264_amd import synth
+    from paper_1107_4264_amd import xcorr as X
+
+    w = STREAM
+    ns, npol, F, C = w["nstation"], w["npol"], w["nchan"], w["chunk"]
+    nin = ns * npol
+    seed = synth.SEED_BASE + w["seed_index"]
+    pool = []
+    for k in range(w["pool"]):
+        d = synth.voltages_torch(seed, C, F, nin, w["dist"], dev, t0=k * C)
+        h = torch.empty(d.shape, dtype=torch.int8, pin_memory=True)
+        h.copy_(d)
+        pool.append(h)
+        del d
+    torch.cuda.synchronize()
+    st = X.Stream(ns, npol, F, C, "ci8", w["path"])
+    out = st.empty_out(dev)
+    chunk_bytes = pool[0].numel()
+    useful = nin * (nin + 1) // 2 * F * C * w["nchunk"]
+
+    def integrate():
+        st.begin(out)
+        for c in range(w["nchunk"]):
+            st.push(pool[c % w["pool"]])
+        st.end()
+
+    steps = max(1, min(args.steps, 3))
+    integrate()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        integrate()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    # the X-engine alone on one resident chunk, for the overlap figure
+    c1 = X.Correlator(ns, npol, F, C, "ci8", w["path"])
+    xd = pool[0].to(dev)
+    o1 = c1.empty_out(dev)
+    for _ in range(3):
+        c1.run(xd, o1)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        c1.run(xd, o1)
+    e1.record()
+    torch.cuda.synchronize()
+    kern_ms = e0.elapsed_time(e1) / 5
+    h2d = chunk_bytes * w["nchunk"] / wall / 1e9
+    tflops = 8.0 * useful / wall / 1e12
+    print(f"[bench] stream: {wall * 1e3:.1f} ms per integration, {h2d:.1f} GB/s host to device, "
+          f"X-engine {kern_ms:.2f} ms per chunk", file=sys.stderr, flush=True)
+    line = {
+        "metric": METRIC, "value": round(tflops, 3), "unit": "TFLOPS", "n_gpus": 1, "steps": steps, "warmup": 1,
+        "ms_per_step": round(wall * 1e3, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "i8", "data": "synthetic",
+        "config": {"workload": w["name"], "chunk_bytes": chunk_bytes, "path": "i8 mfma streaming, int64 totals"},
+        "roofline": {"bound": "host link", "achieved": round(h2d, 2), "peak": None, "unit": "GB/s", "frac": None,
+                     "traffic": None},
+        "xengine_ms_per_chunk": round(kern_ms, 4),
+        "copy_ms_per_chunk": round(wall * 1e3 / w["nchunk"], 4),
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+
+        oracle.build()
+        chans = [0, F // 2, F - 1]
+        got = out[chans].cpu().numpy()
+        want = np.zeros_like(got, dtype=np.int64)
+        t0 = time.perf_counter()
+        for k in range(w["pool"]):
+            xk = synth.voltages_np(seed, C, F, nin, w["dist"], t0=k * C, chans=chans)
+            want += oracle.xcorr(xk, ns, npol, chans=np.arange(len(chans))) * (w["nchunk"] // w["pool"])
+        dt = time.perf_counter() - t0
+        ok = np.array_equal(got.astype(np.int64), want)
+        line["cpu_baseline"] = {"value": round(8.0 * nin * (nin + 1) // 2 * len(chans) * C * w["pool"] / dt / 1e12, 6),
+                                "unit": "TFLOPS", "cores": oracle.num_threads(), "kind": "oracle",
+                                "sample": f"channels {chans} of the {w['pool']} pool chunks, {dt:.2f} s"}
+        line["parity"] = ("totals equal the sum of the chunks' oracle visibilities (linearity) on sampled channels"
+                          if ok else "MISMATCH against the oracle")
+    print(json.dumps(line), flush=True)
+
+
+def batch_cpu_baseline(args, jobs, seed, outs):
+    """The oracle on one channel of jobs taken in a seeded random order until the CPU time
+    budget is spent."""
+    import numpy as np
+
+    import oracle
+    from paper_1107_4264_amd import synth
+
+    oracle.build()
+    rng = np.random.default_rng(1)
+    order = [int(k) for k in rng.permutation(len(jobs))]
+    spent, useful, ok, done = 0.0, 0, True, []
+    for k in order:
+        if spent > args.cpu_seconds and done:
+            break
+        j = jobs[k]
+        nin = j["nstation"] * j["npol"]
+        f = int(rng.integers(j["nchan"]))
+        x = synth.voltages_np(seed + 16 * (k + 1), j["ntime"], j["nchan"], nin, BATCH["dist"], chans=[f])
+        t0 = time.perf_counter()
+        want = oracle.xcorr(x, j["nstation"], j["npol"], chans=[0])
+        spent += time.perf_counter() - t0
+        useful += nin * (nin + 1) // 2 * j["ntime"]
+        ok = ok and np.array_equal(outs[k][f:f + 1].cpu().numpy().astype(np.int64), want)
+        done.append(f"job {int(k)} channel {f}")
+    base = {"value": round(8.0 * useful / spent / 1e12, 6), "unit": "TFLOPS", "cores": 1, "kind": "oracle",
+            "sample": f"one channel of {len(done)} jobs ({', '.join(done)}), {spent:.2f} s"}
+    return base, ok
 
 
 TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",

@@ -369,6 +369,7 @@ struct xcorr_batch {
     int in_fmt = 0, acc = 0, tile = 0, mode = 0, nblocks = 0;
     std::vector<xcorr_job> jobs;
     std::vector<Plan> plans;
+    std::vector<char> whole;  // job runs the whole-channel kernel (its own persistent launch)
     XQueues queues{};
     int64_t nitems = 0;
     XItem *items_dev = nullptr;
@@ -403,6 +404,7 @@ int batch_plan(xcorr_batch *b, int max_abs)
     for (const xcorr_job &j : b->jobs) max_nin = std::max(max_nin, j.nstation * j.npol);
     const int tile = b->acc == ACC_F32_CMAC ? 64 : (max_nin > 64 ? 128 : 64);
     std::vector<Plan> plans(njobs);
+    std::vector<char> whole(njobs, 0);
     std::string err;
     int ci = b->acc == ACC_F32_CMAC ? 4 : ((b->acc == ACC_F8 && b->in_fmt == IN_CI8) ? 4 : 8);
     int mode = LOAD_VEC;
@@ -413,23 +415,39 @@ int batch_plan(xcorr_batch *b, int max_abs)
         const int rc = make_plan(jb.nstation, jb.npol, jb.nchan, jb.ntime, b->in_fmt, b->acc, ma, tile, &plans[j], &err);
         if (rc) return fail(rc, "job " + std::to_string(j) + ": " + err);
         if (b->acc == ACC_F8 && b->in_fmt == IN_CI8 && max_abs == 0) plans[j].max_abs = 128;
-        mode = std::max(mode, load_mode_for(plans[j].nin, b->in_fmt, ci));
+        // jobs the planner gives the whole-channel kernel run it (one launch each); the
+        // others share the persistent launch of the tiled kernel
+        Plan wp;
+        if (b->acc != ACC_F32_CMAC &&
+            make_plan(jb.nstation, jb.npol, jb.nchan, jb.ntime, b->in_fmt, b->acc, ma, 0, &wp, &err) == XCORR_OK &&
+            wp.tile == CHAN_TILE) {
+            wp.max_abs = plans[j].max_abs;
+            plans[j] = wp;
+            whole[j] = 1;
+        } else {
+            mode = std::max(mode, load_mode_for(plans[j].nin, b->in_fmt, ci));
+        }
         if (b->acc != ACC_F32_CMAC &&
             64.0 * (double)jb.nchan * plans[j].nin * (double)in_sample_bytes(b->in_fmt) >= 4294901760.0)
             return fail(XCORR_ERR_RANGE, "job " + std::to_string(j) + ": nchan * nin too large");
     }
-    // work items with a cost estimate (computed pairs of the tile x samples of the window)
-    struct Cost {
+    // Work items in groups of one (job, channel, window): the tiles of a group read the same
+    // input rows, so they stay adjacent in their queue (taken at about the same time by
+    // workgroups of one XCD, whose L2 then serves the re-reads).  Groups are ordered longest
+    // first (cost: computed pairs x samples).
+    struct Group {
         double cost;
-        XItem it;
+        std::vector<XItem> items;
     };
-    std::vector<std::vector<Cost>> q(NQUEUE);
+    std::vector<std::vector<Group>> q(NQUEUE);
     for (int j = 0; j < njobs; ++j) {
         const Plan &pl = plans[j];
+        if (whole[j]) continue;
         for (int f = 0; f < pl.nchan; ++f) {
             const int qq = (int)(((int64_t)j * 131 + f) % NQUEUE);
             for (int w = 0; w < pl.nwindows; ++w) {
                 const int len = std::min(pl.ntime - w * pl.window, pl.window);
+                Group gr{0.0, {}};
                 for (int g = 0; g < pl.tiles_per_chan; ++g) {
                     int64_t bx, by;
                     tile_coords(g, &bx, &by);
@@ -437,17 +455,19 @@ int batch_plan(xcorr_batch *b, int max_abs)
                     const int cols = std::min(pl.tile, pl.nin - (int)bx * pl.tile);
                     double c = (double)rows * cols * len;
                     if (bx == by && b->acc != ACC_F32_CMAC) c *= 0.625;  // lower 32x32 blocks only
-                    q[qq].push_back({c, XItem{j, f, g, w}});
+                    gr.cost += c;
+                    gr.items.push_back(XItem{j, f, g, w});
                 }
+                q[qq].push_back(std::move(gr));
             }
         }
     }
     std::vector<XItem> items;
     XQueues qs{};
     for (int k = 0; k < NQUEUE; ++k) {
-        std::stable_sort(q[k].begin(), q[k].end(), [](const Cost &a, const Cost &c) { return a.cost > c.cost; });
+        std::stable_sort(q[k].begin(), q[k].end(), [](const Group &a, const Group &c) { return a.cost > c.cost; });
         qs.begin[k] = (int64_t)items.size();
-        for (const Cost &c : q[k]) items.push_back(c.it);
+        for (const Group &gr : q[k]) items.insert(items.end(), gr.items.begin(), gr.items.end());
         qs.end[k] = (int64_t)items.size();
     }
     if (b->items_dev) {
@@ -461,6 +481,7 @@ int batch_plan(xcorr_batch *b, int max_abs)
         if (e != hipSuccess) return hip_fail((int)e, "upload work list");
     }
     b->plans = plans;
+    b->whole = whole;
     b->tile = tile;
     b->mode = mode;
     b->queues = qs;
@@ -536,7 +557,8 @@ int xcorr_batch_run(xcorr_batch_t *b, const void *const *in, void *const *out, h
     }
     for (int j = 0; j < njobs; ++j) {
         XJob jb = job_from_plan(b->plans[j], in[j], out[j]);
-        jb.load_mode = b->mode;
+        // the launch's mode covers every job; a word-load launch keeps chunk loads per job
+        if (!(b->mode == LOAD_WORD && jb.load_mode == LOAD_VEC)) jb.load_mode = b->mode;
         b->jobs_pinned[j] = jb;
     }
     if ((e = hipMemcpyAsync(b->jobs_dev, b->jobs_pinned, njobs * sizeof(XJob), hipMemcpyHostToDevice, stream)) !=
@@ -550,6 +572,11 @@ int xcorr_batch_run(xcorr_batch_t *b, const void *const *in, void *const *out, h
         if (b->plans[j].nwindows != 1) {
             rc = launch_zero(out[j], b->plans[j].out_bytes, stream);
             if (rc) return hip_fail(rc, "zero fill");
+        }
+    for (int j = 0; j < njobs; ++j)
+        if (b->whole[j]) {
+            rc = launch_job(b->plans[j], job_from_plan(b->plans[j], in[j], out[j]), stream);
+            if (rc) return hip_fail(rc, "whole-channel launch of a batch job");
         }
     if (b->nitems == 0) return XCORR_OK;
     rc = b->acc == ACC_F32_CMAC

@@ -623,7 +623,14 @@ __global__ __launch_bounds__(NTHREADS, 2) void xeng_mfma_batch_kernel(const XJob
             __syncthreads();
             if (it >= q.end[qq]) break;
             const XItem item = items[it];
-            process_item<ACC, IN, TILE, MODE>(jobs[item.job], item.chan, item.tile, item.window, lds);
+            const XJob &jb = jobs[item.job];
+            // a word-load launch still runs the jobs whose rows allow 16-byte chunks with them
+            if constexpr (MODE == LOAD_WORD) {
+                if (jb.load_mode == LOAD_VEC) process_item<ACC, IN, TILE, LOAD_VEC>(jb, item.chan, item.tile, item.window, lds);
+                else process_item<ACC, IN, TILE, LOAD_WORD>(jb, item.chan, item.tile, item.window, lds);
+            } else {
+                process_item<ACC, IN, TILE, MODE>(jb, item.chan, item.tile, item.window, lds);
+            }
         }
     }
 }
