@@ -68,8 +68,6 @@ struct Geom {
     static constexpr int QUADS = TB / 4;                    // 4-sample groups per block
     static constexpr int FBUF = STAGE ? QUADS * 256 * 16 : 0;  // staged operand bytes
     static constexpr int LDS = RING * BLK + 2 * FBUF;
-    // conversion: 16 groups of 16 inputs x QUADS per block, four per wave instruction
-    static constexpr int NCONV = STAGE ? 16 * QUADS / 4 / (CT / 64) : 0;
 };
 
 template <int ACC>
@@ -155,9 +153,10 @@ __device__ __forceinline__ Frag<4> op_rot(const Frag<4> &a)
                 o.w[k] = __builtin_bit_cast(uint32_t, v);
             }
         } else {
-            const f16x2 v = __builtin_bit_cast(f16x2, a.w[k]);
-            const f16x2 sgn = COL ? (f16x2){(_Float16)(-1.0f), (_Float16)1.0f} : (f16x2){(_Float16)1.0f, (_Float16)(-1.0f)};
-            o.w[k] = __builtin_bit_cast(uint32_t, __builtin_shufflevector(v, v, 1, 0) * sgn);
+            // one packed multiply: low half = high half x sign.lo, high half = low half x
+            // sign.hi (op_sel picks the swapped halves of the operand)
+            const uint32_t sgn = COL ? 0x3C00BC00u : 0xBC003C00u;  // (-1, 1) or (1, -1)
+            asm("v_pk_mul_f16 %0, %1, %2 op_sel:[1,0] op_sel_hi:[0,1]" : "=v"(o.w[k]) : "v"(a.w[k]), "s"(sgn));
         }
     }
     return o;
@@ -363,7 +362,7 @@ struct Cursor {
     __device__ __forceinline__ void init(const XJob &p) { set(p, blockIdx.x); }
     __device__ __forceinline__ void next(const XJob &p)
     {
-        if (++blk == nblk) set(p, item + gridDim.x);
+        if (++blk == nblk) set(p, item + p.grid);
     }
 };
 
@@ -457,27 +456,89 @@ struct AccSet {
 
 // ---------------------------------------------------------------- kernel
 
-// One K-step of wave W: read its fragments, form the operands, issue 2 NB MFMAs.
-template <int ACC, int W, int KSTEP>
-__device__ __forceinline__ void kstep(const uint32_t (&lv)[4], AccSet<ACC> &acc)
+// Position of the n-th fragment of wave W that is also needed rotated, and their count.
+template <int W>
+constexpr int rot_index(int n)
+{
+    int c = 0;
+    for (int x = 0; x < Spec<W>::NF; ++x)
+        if (Spec<W>::ROT[x]) {
+            if (c == n) return x;
+            ++c;
+        }
+    return -1;
+}
+template <int W>
+constexpr int rot_count()
+{
+    int c = 0;
+    for (int x = 0; x < Spec<W>::NF; ++x) c += Spec<W>::ROT[x] ? 1 : 0;
+    return c;
+}
+
+// The 2 NB MFMAs of one K-step of wave W from its plain operand fragments A: the real
+// parts first, each of the first ones followed by the rotation of one fragment (vector ALU
+// work that runs while the matrix cores are busy), then the imaginary parts.  `early` (copy
+// issue) runs after the first MFMA and `mid` (more vector work) after the second
+// imaginary-part MFMA.  The scheduling barriers keep this order.
+template <int ACC, int W, typename Early, typename Mid>
+__device__ __forceinline__ void mma_step(const Frag<4> (&A)[Spec<W>::NF], AccSet<ACC> &acc, Early &&early, Mid &&mid)
 {
     using S = Spec<W>;
-    Raw<ACC> r[S::NF];
-    static_for<S::NF>([&](auto X) __attribute__((always_inline)) {
-        constexpr int x = decltype(X)::value;
-        r[x] = read_frag<ACC, S::F[x], KSTEP>(lv);
-    });
-    Frag<4> A[S::NF], Rt[S::NF];
-    static_for<S::NF>([&](auto X) __attribute__((always_inline)) {
-        constexpr int x = decltype(X)::value;
-        A[x] = op_plain<ACC>(r[x]);
-        if constexpr (S::ROT[x]) Rt[x] = op_rot<ACC, !S::ROWROT>(A[x]);
-    });
+    constexpr int NROT = rot_count<W>();
+    static_assert(NROT <= S::NB, "rotations ride on the real-part MFMAs");
+    Frag<4> Rt[S::NF];
     static_for<S::NB>([&](auto B) __attribute__((always_inline)) {
         constexpr int b = decltype(B)::value;
         mma(acc.re[b], A[S::BR[b]], A[S::BC[b]]);
+        if constexpr (b == 0) early();
+        if constexpr (b < NROT) {
+            constexpr int x = rot_index<W>(b);
+            Rt[x] = op_rot<ACC, !S::ROWROT>(A[x]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    });
+    static_for<S::NB>([&](auto B) __attribute__((always_inline)) {
+        constexpr int b = decltype(B)::value;
         if constexpr (S::ROWROT) mma(acc.im[b], Rt[S::BR[b]], A[S::BC[b]]);
         else mma(acc.im[b], A[S::BR[b]], Rt[S::BC[b]]);
+        if constexpr (b == 1) mid();
+        __builtin_amdgcn_sched_barrier(0);
+    });
+}
+
+// Transposing reads of the raw fragments wave W needs at K-step KSTEP.
+template <int ACC, int W, int KSTEP>
+__device__ __forceinline__ void read_step(const uint32_t (&lv)[4], Raw<ACC> (&r)[Spec<W>::NF])
+{
+    static_for<Spec<W>::NF>([&](auto X) __attribute__((always_inline)) {
+        constexpr int x = decltype(X)::value;
+        r[x] = read_frag<ACC, Spec<W>::F[x], KSTEP>(lv);
+    });
+}
+
+// All K-steps of one block on raw operands, software pipelined: the reads of K-step k + 1
+// are issued before the MFMAs of K-step k, so that a wave keeps its matrix core busy while
+// the other wave of its SIMD waits at the barrier.  copy(k) issues the copies due at
+// K-step k.
+template <int ACC, int W, int NKS, typename Copy>
+__device__ __forceinline__ void block_raw(const uint32_t (&lv)[4], AccSet<ACC> &acc, Copy &&copy)
+{
+    using S = Spec<W>;
+    Raw<ACC> ra[S::NF], rb[S::NF];
+    read_step<ACC, W, 0>(lv, ra);
+    static_for<NKS>([&](auto K) __attribute__((always_inline)) {
+        constexpr int k = decltype(K)::value;
+        Raw<ACC>(&cur)[S::NF] = (k & 1) ? rb : ra;
+        Raw<ACC>(&nxt)[S::NF] = (k & 1) ? ra : rb;
+        if constexpr (k + 1 < NKS) read_step<ACC, W, k + 1>(lv, nxt);
+        __builtin_amdgcn_sched_barrier(0);
+        Frag<4> A[S::NF];
+        static_for<S::NF>([&](auto X) __attribute__((always_inline)) {
+            constexpr int x = decltype(X)::value;
+            A[x] = op_plain<ACC>(cur[x]);
+        });
+        mma_step<ACC, W>(A, acc, [&]() __attribute__((always_inline)) { copy(K); }, [] {});
     });
 }
 
@@ -515,27 +576,15 @@ extern __shared__ __attribute__((aligned(16))) uint8_t chan_lds[];
 
 typedef __attribute__((address_space(3))) u32x4 lds_u4;
 
-// One K-step of wave W on staged fp16 operands: fragment of block row R for K-step KSTEP at
-// lvf + 8192 KSTEP + 512 R (lvf: this lane's unit of the buffer, see run_wave).
-template <int ACC, int W, int KSTEP>
-__device__ __forceinline__ void kstep_staged(uint32_t lvf, AccSet<ACC> &acc)
+// Staged fp16 fragment of block row R for K-step KSTEP at lvf + 8192 KSTEP + 512 R (lvf:
+// this lane's unit of the buffer, see run_wave).
+template <int W, int KSTEP>
+__device__ __forceinline__ void read_staged(uint32_t lvf, Frag<4> (&A)[Spec<W>::NF])
 {
-    using S = Spec<W>;
-    Frag<4> A[S::NF], Rt[S::NF];
-    static_for<S::NF>([&](auto X) __attribute__((always_inline)) {
+    static_for<Spec<W>::NF>([&](auto X) __attribute__((always_inline)) {
         constexpr int x = decltype(X)::value;
-        const u32x4 v = *(const lds_u4 *)(uintptr_t)(lvf + (uint32_t)(KSTEP * 8192 + S::F[x] * 512));
+        const u32x4 v = *(const lds_u4 *)(uintptr_t)(lvf + (uint32_t)(KSTEP * 8192 + Spec<W>::F[x] * 512));
         A[x].w[0] = v[0]; A[x].w[1] = v[1]; A[x].w[2] = v[2]; A[x].w[3] = v[3];
-    });
-    static_for<S::NF>([&](auto X) __attribute__((always_inline)) {
-        constexpr int x = decltype(X)::value;
-        if constexpr (S::ROT[x]) Rt[x] = op_rot<ACC, !S::ROWROT>(A[x]);
-    });
-    static_for<S::NB>([&](auto B) __attribute__((always_inline)) {
-        constexpr int b = decltype(B)::value;
-        mma(acc.re[b], A[S::BR[b]], A[S::BC[b]]);
-        if constexpr (S::ROWROT) mma(acc.im[b], Rt[S::BR[b]], A[S::BC[b]]);
-        else mma(acc.im[b], A[S::BR[b]], Rt[S::BC[b]]);
     });
 }
 
@@ -565,6 +614,16 @@ __device__ __forceinline__ void run_wave(const XJob &p, int lane)
 #pragma unroll
         for (int m = 0; m < DPW; ++m) dma16(rs, dst + 2 * m * CROW, voff[m]);
     };
+    // The copies of one block spread over the K-steps of the block being multiplied:
+    // instruction m at K-step m NKS / DPW, among the MFMAs (all of them leaving the barrier
+    // at once would queue behind each other).
+    auto copy_at = [&](auto K, const i32x4s &rs, uint32_t dst) __attribute__((always_inline)) {
+        constexpr int k = decltype(K)::value;
+        static_for<DPW>([&](auto M) __attribute__((always_inline)) {
+            constexpr int m = decltype(M)::value;
+            if constexpr (m * NKS / DPW == k) dma16(rs, dst + 2 * m * CROW, voff[m]);
+        });
+    };
 
     AccSet<ACC> acc;
 #pragma unroll
@@ -579,7 +638,7 @@ __device__ __forceinline__ void run_wave(const XJob &p, int lane)
             acc.re[x] = (typename O::acc_t){};
             acc.im[x] = (typename O::acc_t){};
         }
-        cc.set(p, cc.item + gridDim.x);
+        cc.set(p, cc.item + p.grid);
     };
 
     Cursor<TB> dc, cc;
@@ -605,13 +664,14 @@ __device__ __forceinline__ void run_wave(const XJob &p, int lane)
             if (ready == 0) wait_vm<(RING - 2) * DPW>();
             else --ready;
             __syncthreads();
-            issue(dc, slot == 0 ? RING - 1 : slot - 1);
+            const i32x4s rs = block_rsrc<TB>(p, dc, row_stride);
+            const uint32_t dst = lds0 + (slot == 0 ? RING - 1 : slot - 1) * G::BLK + 2 * DPW * W * CROW;
             dc.next(p);
 
             uint32_t lv[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) lv[q] = lb[q] + slot * G::BLK;
-            static_for<NKS>([&](auto K) __attribute__((always_inline)) { kstep<ACC, W, decltype(K)::value>(lv, acc); });
+            block_raw<ACC, W, NKS>(lv, acc, [&](auto K) __attribute__((always_inline)) { copy_at(K, rs, dst); });
             slot = slot == RING - 1 ? 0 : slot + 1;
 
             if (++cc.blk == cc.nblk) {
@@ -623,37 +683,46 @@ __device__ __forceinline__ void run_wave(const XJob &p, int lane)
     } else {
         // Staged operands: the block after the one being multiplied is converted into the
         // other buffer (unit of input i and samples 4q..4q+3 at 4096 q + 16 i), read from the
-        // raw ring with transposing reads: instruction u of this wave covers 16-input groups
-        // ig = c % 16 at sample groups q = c / 16, c = 4 (NCONV W + u) + lane / 16.
+        // raw ring with transposing reads.  Only the waves with five blocks (0..3) convert:
+        // the four-block waves share their SIMDs with them and are the ones the barriers
+        // wait for.  Instruction u of converting wave W covers the 16-input group
+        // ig = 4 (u % 4) + lane / 16 at sample group q = 2 W + u / 4; units u and u + 4 differ
+        // by four sample rows.
+        constexpr int CW = 4;                          // converting waves
+        constexpr int UPW = 16 * G::QUADS / 4 / CW;    // conversion instructions per converting wave
+        static_assert(UPW == 2 * NKS, "two conversion units per K-step");
         const uint32_t fb0 = lds0 + RING * G::BLK;
-        uint32_t cin[G::NCONV], cout[G::NCONV];
+        uint32_t cin[4], cout[4];
 #pragma unroll
-        for (int u = 0; u < G::NCONV; ++u) {
-            const int c = 4 * (G::NCONV * W + u) + (lane >> 4);
-            const int ig = c & 15, q = c >> 4;
+        for (int j = 0; j < 4; ++j) {
+            const int ig = 4 * j + (lane >> 4), q = (UPW / 4) * (W < CW ? W : 0);
             const int k = (lane >> 2) & 3, a = lane & 3;
             const int row = 4 * q + k;
             const int chunk = (2 * ig + (a >> 1)) ^ (4 * k);
-            cin[u] = (uint32_t)(row * CROW + 16 * chunk + 8 * (a & 1));
-            cout[u] = (uint32_t)(4096 * q + 16 * (16 * ig + (lane & 15)));
+            cin[j] = (uint32_t)(row * CROW + 16 * chunk + 8 * (a & 1));
+            cout[j] = (uint32_t)(4096 * q + 16 * (16 * ig + (lane & 15)));
         }
-        auto convert_unit = [&](int u, uint32_t src, uint32_t dst) __attribute__((always_inline)) {
-            const s16x4 v = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4 *)(uintptr_t)(src + cin[u]));
+        auto convert_read = [&](int u, uint32_t src) __attribute__((always_inline)) {
+            return __builtin_amdgcn_ds_read_tr16_b64_v4i16(
+                (lds_s16x4 *)(uintptr_t)(src + cin[u & 3] + (uint32_t)((u >> 2) * 4 * CROW)));
+        };
+        auto convert_write = [&](int u, s16x4 v, uint32_t dst) __attribute__((always_inline)) {
             const uint2 w = __builtin_bit_cast(uint2, v);
             uint32_t o0, o1, o2, o3;
             f16_pairs(w.x, o0, o1);
             f16_pairs(w.y, o2, o3);
-            *(lds_u4 *)(uintptr_t)(dst + cout[u]) = (u32x4){o0, o1, o2, o3};
+            *(lds_u4 *)(uintptr_t)(dst + cout[u & 3] + (uint32_t)((u >> 2) * 4096)) = (u32x4){o0, o1, o2, o3};
         };
-        static_assert(G::NCONV == NKS, "one conversion unit per K-step");
         // this lane's unit of a staged fragment: sample group 2 KSTEP + lane / 32, input
         // 32 R + lane % 32
         const uint32_t lf = (uint32_t)(4096 * (lane >> 5) + 16 * (lane & 31));
 
         wait_vm<(RING - 2) * DPW>();
         __syncthreads();
+        if constexpr (W < CW) {
 #pragma unroll
-        for (int u = 0; u < G::NCONV; ++u) convert_unit(u, lds0, fb0);
+            for (int u = 0; u < UPW; ++u) convert_write(u, convert_read(u, lds0), fb0);
+        }
         int slot = 0, fb = 0;
         int ready = 0;
         while (cc.valid) {
@@ -663,17 +732,39 @@ __device__ __forceinline__ void run_wave(const XJob &p, int lane)
             if (ready == 0) wait_vm<(RING - 3) * DPW>();
             else --ready;
             __syncthreads();
-            issue(dc, slot == 0 ? RING - 1 : slot - 1);
+            const i32x4s rs = block_rsrc<TB>(p, dc, row_stride);
+            const uint32_t dst = lds0 + (slot == 0 ? RING - 1 : slot - 1) * G::BLK + 2 * DPW * W * CROW;
             dc.next(p);
 
-            // multiply this block, converting one unit of the next after each K-step so that
-            // the conversion overlaps the matrix cores
+            // multiply this block, software pipelined: at each K-step the reads of the next
+            // K-step's fragments and of two conversion units of the next block are issued
+            // before the MFMAs, and the units are converted and stored between them
             const uint32_t lvf = fb0 + fb * G::FBUF + lf;
             const uint32_t csrc = lds0 + (slot == RING - 1 ? 0 : slot + 1) * G::BLK, cdst = fb0 + (fb ^ 1) * G::FBUF;
-            static_for<NKS>([&](auto K) __attribute__((always_inline)) {
-                kstep_staged<ACC, W, decltype(K)::value>(lvf, acc);
-                convert_unit(decltype(K)::value, csrc, cdst);
-            });
+            {
+                using S = Spec<W>;
+                Frag<4> fa[S::NF], fbk[S::NF];
+                read_staged<W, 0>(lvf, fa);
+                static_for<NKS>([&](auto K) __attribute__((always_inline)) {
+                    constexpr int k = decltype(K)::value;
+                    Frag<4>(&cur)[S::NF] = (k & 1) ? fbk : fa;
+                    Frag<4>(&nxt)[S::NF] = (k & 1) ? fa : fbk;
+                    s16x4 cv0, cv1;
+                    if constexpr (W < CW) {
+                        cv0 = convert_read(2 * k, csrc);
+                        cv1 = convert_read(2 * k + 1, csrc);
+                    }
+                    if constexpr (k + 1 < NKS) read_staged<W, k + 1>(lvf, nxt);
+                    __builtin_amdgcn_sched_barrier(0);
+                    mma_step<ACC, W>(cur, acc, [&]() __attribute__((always_inline)) { copy_at(K, rs, dst); },
+                                     [&]() __attribute__((always_inline)) {
+                                         if constexpr (W < CW) {
+                                             convert_write(2 * k, cv0, cdst);
+                                             convert_write(2 * k + 1, cv1, cdst);
+                                         }
+                                     });
+                });
+            }
             slot = slot == RING - 1 ? 0 : slot + 1;
             fb ^= 1;
 
@@ -693,24 +784,30 @@ __global__ __launch_bounds__(CT, 1) void xeng_chan_kernel(XJob p)
 {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
+    // Waves w and w + 4 share a SIMD and the older one (w) wins its issue conflicts.  The
+    // fp16 path gives it the five-block list and the conversion; the int8 path runs faster
+    // with the four-block squares on the older waves.
+    constexpr int X = ACC == ACC_I8 ? 4 : 0;
     switch (wave) {
-    case 0: run_wave<ACC, 0>(p, lane); break;
-    case 1: run_wave<ACC, 1>(p, lane); break;
-    case 2: run_wave<ACC, 2>(p, lane); break;
-    case 3: run_wave<ACC, 3>(p, lane); break;
-    case 4: run_wave<ACC, 4>(p, lane); break;
-    case 5: run_wave<ACC, 5>(p, lane); break;
-    case 6: run_wave<ACC, 6>(p, lane); break;
-    default: run_wave<ACC, 7>(p, lane); break;
+    case 0: run_wave<ACC, 0 ^ X>(p, lane); break;
+    case 1: run_wave<ACC, 1 ^ X>(p, lane); break;
+    case 2: run_wave<ACC, 2 ^ X>(p, lane); break;
+    case 3: run_wave<ACC, 3 ^ X>(p, lane); break;
+    case 4: run_wave<ACC, 4 ^ X>(p, lane); break;
+    case 5: run_wave<ACC, 5 ^ X>(p, lane); break;
+    case 6: run_wave<ACC, 6 ^ X>(p, lane); break;
+    default: run_wave<ACC, 7 ^ X>(p, lane); break;
     }
 }
 
-template <typename K>
-int allow_lds_chan(K kernel, int bytes)
+// Dynamic LDS beyond the default limit, set once per kernel (one flag per path).
+template <int ACC>
+int allow_lds_chan()
 {
     static int done = 0;
     if (!done) {
-        const hipError_t e = hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        const hipError_t e = hipFuncSetAttribute((const void *)xeng_chan_kernel<ACC>,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, Geom<ACC>::LDS);
         if (e != hipSuccess) return (int)e;
         done = 1;
     }
@@ -721,7 +818,7 @@ template <int ACC>
 int launch_chan_acc(const XJob &job, hipStream_t stream)
 {
     auto k = xeng_chan_kernel<ACC>;
-    if (int e = allow_lds_chan(k, Geom<ACC>::LDS)) return e;
+    if (int e = allow_lds_chan<ACC>()) return e;
     hipLaunchKernelGGL(k, dim3((unsigned)job.grid), dim3(CT), Geom<ACC>::LDS, stream, job);
     return (int)hipGetLastError();
 }
