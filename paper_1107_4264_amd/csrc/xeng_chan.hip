@@ -8,22 +8,24 @@
 // this memory system.  The workgroup is persistent: it walks channels (and accumulation
 // windows) blockIdx.x, blockIdx.x + gridDim.x, ... with one workgroup per compute unit.
 //
-// Data path for one block of 64 time rows:
-//   * the rows are copied from HBM straight into a four-block LDS ring by buffer loads
-//     with the LDS-destination bit (no registers involved), three blocks ahead of the
-//     block being multiplied; the 16-byte chunks of a row are XOR-swizzled by the row
-//     index so that the transposing reads below are free of bank conflicts;
+// Data path for one block of time rows (64 for int8, 32 for fp16):
+//   * the rows are copied from HBM straight into an LDS ring by buffer loads with the
+//     LDS-destination bit (no registers involved), three blocks ahead of the block being
+//     multiplied; the 16-byte chunks of a row are XOR-swizzled by the row index so that
+//     the transposing reads below are free of bank conflicts;
 //   * MFMA operands are read with ds_read_b64_tr_b16: one complex 8-bit sample is one
 //     16-bit element, so the transposing read hands each lane four consecutive samples of
-//     one input, which is the operand layout of a 32-row MFMA fragment;
+//     one input, which is the operand layout of a 32-row MFMA fragment (the fp16 path
+//     converts each block once, exactly, into an fp16 operand buffer read with 16-byte
+//     reads);
 //   * the complex product is mapped to real MFMAs as in the tiled kernel: the real part is
 //     the product of the (re, im) pair sequences and the imaginary part the product with
-//     the column pairs rotated to (-im, re) (Eq. 5, four real MACs per complex MAC);
-//     the fp16 path converts the int8 pairs exactly to fp16 while forming the operands.
-// Work split (register level of the hierarchy of Sec. 4.1): four waves, one per SIMD, nine
-// 32x32 blocks each: block rows {5,6,7} x columns {0,1,2}, rows {2,3,4} x columns {0,1,2},
-// rows {5,6,7} x columns {3,4,5}, and the three diagonal triangles of rows {0,1}, {3,4},
-// {6,7}.  Every wave issues 18 MFMAs per K-step from six operand fragments.
+//     one side rotated to (-im, re) or (im, -re) (Eq. 5, four real MACs per complex MAC).
+// Work split (register level of the hierarchy of Sec. 4.1): eight waves, two per SIMD,
+// 36 blocks of 32x32 baselines: four lists of five blocks (a diagonal 2x2 triangle plus a
+// two-block strip) and four off-diagonal 2x2 squares, so every SIMD carries nine blocks.
+// Each K-step is software pipelined: the next K-step's operand reads are issued before the
+// current MFMAs.
 
 #include <hip/hip_runtime.h>
 
