@@ -635,13 +635,14 @@ __global__ __launch_bounds__(NTHREADS, 2) void xeng_mfma_batch_kernel(const XJob
     }
 }
 
-// Kernels use more than the default 64 KiB of dynamic LDS; raise the limit once per kernel.
-template <typename K>
-int allow_lds(K kernel, int bytes)
+// Kernels use more than the default 64 KiB of dynamic LDS; raise the limit once per kernel
+// (the kernel is a template argument, so every kernel has its own flag).
+template <auto Kernel>
+int allow_lds(int bytes)
 {
-    static int done = 0;  // one static per kernel instantiation
+    static int done = 0;
     if (!done) {
-        const hipError_t e = hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        const hipError_t e = hipFuncSetAttribute((const void *)Kernel, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
         if (e != hipSuccess) return (int)e;
         done = 1;
     }
@@ -653,7 +654,7 @@ int launch_mode(const XJob &job, hipStream_t stream)
 {
     constexpr int LDS = Tile<ACC, IN, TILE>::LDS_BYTES;
     auto k = xeng_mfma_kernel<ACC, IN, TILE, MODE>;
-    if (int e = allow_lds(k, LDS)) return e;
+    if (int e = allow_lds<xeng_mfma_kernel<ACC, IN, TILE, MODE>>(LDS)) return e;
     hipLaunchKernelGGL(k, dim3((unsigned)job.grid), dim3(NTHREADS), LDS, stream, job);
     return (int)hipGetLastError();
 }
@@ -672,7 +673,7 @@ int launch_batch(const XJob *jobs, const XItem *items, const XQueues &q, unsigne
 {
     constexpr int LDS = Tile<ACC, IN, TILE>::LDS_BYTES;
     auto k = xeng_mfma_batch_kernel<ACC, IN, TILE, MODE>;
-    if (int e = allow_lds(k, LDS)) return e;
+    if (int e = allow_lds<xeng_mfma_batch_kernel<ACC, IN, TILE, MODE>>(LDS)) return e;
     hipLaunchKernelGGL(k, dim3(nblocks), dim3(NTHREADS), LDS, stream, jobs, items, q, counters);
     return (int)hipGetLastError();
 }
