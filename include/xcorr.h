@@ -117,18 +117,23 @@ xcorr_handle_t *xcorr_create(int nstation, int npol, int nchan, int ntime,
 int xcorr_set_max_abs(xcorr_handle_t *h, int max_abs);
 
 /* Choose the kernel shape (Sec. 4.2's tiling of the triangle, re-planned for gfx950):
- *   0    automatic (the default): 256 when allowed and nin > 192, else 128 (64 when
- *        nin <= 64; always 64 for F32_CMAC);
+ *   0    automatic (the default): 512 when allowed, else 256 when allowed and nin > 192,
+ *        else 128 (64 when nin <= 64; always 64 for F32_CMAC);
  *   64, 128  square tiles of that many inputs, one workgroup per (channel, tile, window);
  *   256  whole channel: one persistent workgroup per compute unit holds the triangle of a
  *        channel and reads every sample once; needs CI8 input, the int8 or fp16 path and
  *        nin <= 256, a multiple of 8.  An input pointer that is not 16-byte aligned runs
- *        128-tiles instead.
+ *        128-tiles instead;
+ *   512  super-tiles: the triangle of each channel cut into 256-input triangles and
+ *        256 x 128 rectangles, each held by one persistent workgroup (two launches); needs
+ *        CI4 input, the int8 path, nin a multiple of 256 in 512..2048 and
+ *        ntime <= (2^31 - 1) / (128 max_abs^2) (the operands are the samples times 8).
+ *        Same alignment fallback.
  * All shapes give bit-identical visibilities.  XCORR_ERR_INVALID_ARG for a shape the job
  * does not allow (the handle keeps its previous shape). */
 int xcorr_set_tile(xcorr_handle_t *h, int tile);
 
-/* The kernel shape the handle runs (64, 128 or 256), or an error code. */
+/* The kernel shape the handle runs (64, 128, 256 or 512), or an error code. */
 int xcorr_get_tile(const xcorr_handle_t *h);
 
 /* Autotuner (the tile-size search of Sec. 4.2 / 6, done on the device): run every kernel

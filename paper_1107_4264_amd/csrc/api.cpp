@@ -78,10 +78,11 @@ XJob job_from_plan(const Plan &pl, const void *in, void *out)
 // 2^24 blocks.
 int launch_job(const Plan &pl, XJob j, hipStream_t stream)
 {
-    if (pl.tile == CHAN_TILE) {
+    if (pl.tile == CHAN_TILE || pl.tile == SUPER_TILE) {
         if ((uintptr_t)j.in % 16 == 0) {
             const int cus = device_cus();
             if (cus <= 0) return (int)hipErrorNoDevice;
+            if (pl.tile == SUPER_TILE) return launch_super(j, cus, stream);
             j.grid = std::min<int64_t>(pl.nitems, cus);
             return launch_chan(j, pl.acc, stream);
         }
@@ -250,7 +251,7 @@ int xcorr_autotune(xcorr_handle_t *h, const void *in, void *out, hipStream_t str
     if (reps < 1 || reps > 1000) return fail(XCORR_ERR_INVALID_ARG, "reps must be in 1..1000");
     const Plan &o = h->plan;
     std::vector<Plan> cand;
-    for (int t : {CHAN_TILE, 128, 64}) {
+    for (int t : {SUPER_TILE, CHAN_TILE, 128, 64}) {
         Plan q;
         std::string err;
         if (make_plan(o.nstation, o.npol, o.nchan, o.ntime, o.in_fmt, o.acc, o.max_abs, t, &q, &err) == XCORR_OK) {

@@ -75,10 +75,24 @@ bool chan_kernel_ok(int nin, int in_fmt, int acc)
     return in_fmt == IN_CI8 && (acc == ACC_I8 || acc == ACC_F16) && nin % 8 == 0 && nin >= 1 && nin <= CHAN_TILE;
 }
 
+bool super_kernel_ok(int nin, int nchan, int64_t ntime, int in_fmt, int acc, int max_abs)
+{
+    if (in_fmt != IN_CI4 || acc != ACC_I8 || nin % 256 != 0 || nin < 512 || nin > 2048) return false;
+    // the copy offsets of a block (32 rows) stay below 2^32 bytes
+    if (32 * (int64_t)nchan * nin >= ((int64_t)1 << 32)) return false;
+    const int64_t m = max_abs;
+    return m >= 1 && ntime <= (int64_t)2147483647 / (128 * m * m);
+}
+
 int64_t computed_pairs_per_sample(int nin, int tile, int acc)
 {
     // whole-channel kernel: all 36 blocks of the 8x8-block triangle, whatever nin
     if (tile == CHAN_TILE) return 36 * 32 * 32;
+    // super-tiles: S triangles of 36 blocks and S (S - 1) rectangles of 32 blocks
+    if (tile == SUPER_TILE) {
+        const int64_t s = nin / 256;
+        return (s * 36 + s * (s - 1) * 32) * 32 * 32;
+    }
     const int64_t nts = (nin + tile - 1) / tile;
     if (acc == ACC_F32_CMAC) return nts * (nts + 1) / 2 * (int64_t)tile * tile;
     // MFMA kernels: 32x32 blocks, skipping blocks strictly above the diagonal of a diagonal
@@ -142,22 +156,34 @@ int make_plan(int nstation, int npol, int nchan, int ntime, int in_fmt, int acc,
     // Above 192 inputs the whole-channel kernel computes at most 36/28 of the useful blocks
     // and reads every sample once, in whole rows.
     if (chan_kernel_ok(p.nin, in_fmt, acc) && p.nin > 192) tile = CHAN_TILE;
+    // From 512 inputs of 4-bit samples on the int8 path, super-tiles: whole 256-input
+    // pieces per workgroup, operands widened once per block in LDS.
+    if (super_kernel_ok(p.nin, nchan, ntime, in_fmt, acc, max_abs)) tile = SUPER_TILE;
     if (tile_override) {
         bool ok;
         if (acc == ACC_F32_CMAC) ok = tile_override == 64;
         else if (tile_override == CHAN_TILE) ok = chan_kernel_ok(p.nin, in_fmt, acc);
+        else if (tile_override == SUPER_TILE) ok = super_kernel_ok(p.nin, nchan, ntime, in_fmt, acc, max_abs);
         else ok = tile_override == 64 || tile_override == 128;
         if (!ok) {
             *err = tile_override == CHAN_TILE
                        ? "tile 256 (whole channel) needs CI8 input, the int8 or fp16 path and nin <= 256, a multiple of 8"
+                   : tile_override == SUPER_TILE
+                       ? "tile 512 (super-tiles) needs CI4 input, the int8 path, nin a multiple of 256 in 512..2048 "
+                         "and ntime <= (2^31-1) / (128 max_abs^2)"
                        : "unsupported tile size";
             return XCORR_ERR_INVALID_ARG;
         }
         tile = tile_override;
     }
     p.tile = tile;
-    p.ntile_side = tile == CHAN_TILE ? 1 : (p.nin + tile - 1) / tile;
-    p.tiles_per_chan = p.ntile_side * (p.ntile_side + 1) / 2;
+    if (tile == SUPER_TILE) {
+        p.ntile_side = p.nin / 256;                        // super-rows
+        p.tiles_per_chan = p.ntile_side * p.ntile_side;    // triangles + rectangles
+    } else {
+        p.ntile_side = tile == CHAN_TILE ? 1 : (p.nin + tile - 1) / tile;
+        p.tiles_per_chan = p.ntile_side * (p.ntile_side + 1) / 2;
+    }
 
     const int64_t lim = window_limit(in_fmt, acc, in_fmt == IN_CF32 ? 1 : max_abs);
     if (ntime <= lim) {

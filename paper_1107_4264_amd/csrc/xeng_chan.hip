@@ -166,14 +166,14 @@ __device__ __forceinline__ Frag<4> op_rot(const Frag<4> &a)
 
 // Transposing reads of the fragment of block row R for K-step KSTEP from the ring slot
 // whose per-lane addresses are lv[] (see lane_bases).
-template <int ACC, int R, int KSTEP>
+template <int ACC, int R, int KSTEP, int ROWB = CROW>
 __device__ __forceinline__ Raw<ACC> read_frag(const uint32_t (&lv)[4])
 {
     using O = COp<ACC>;
     Raw<ACC> r;
 #pragma unroll
     for (int e = 0; e < O::NREAD; ++e) {
-        const uint32_t imm = (uint32_t)((KSTEP * O::KS + 4 * e) * CROW + 256 * (R >> 2));
+        const uint32_t imm = (uint32_t)((KSTEP * O::KS + 4 * e) * ROWB + 256 * (R >> 2));
         const s16x4 v = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4 *)(uintptr_t)(lv[R & 3] + imm));
         const uint2 u = __builtin_bit_cast(uint2, v);
         r.w[2 * e] = u.x;
@@ -186,14 +186,14 @@ __device__ __forceinline__ Raw<ACC> read_frag(const uint32_t (&lv)[4])
 // points at time row 4k' + k of its half (h = l / 32 selects samples 4*NREAD*h ..), input
 // 32R + 16(g % 2) + 4a; chunk c = 4R + 2(g % 2) + a / 2 of the row sits at chunk c ^ 4k,
 // i.e. at 4(R ^ k) + j: for R & 3 = q that is 64(q ^ k) + 16j, plus 256 for R >= 4.
-template <int ACC>
+template <int ACC, int ROWB = CROW>
 __device__ __forceinline__ uint32_t lane_base(int lane, int q)
 {
     using O = COp<ACC>;
     const int h = lane >> 5;
     const int k = (lane >> 2) & 3;
     const int j = 2 * ((lane >> 4) & 1) + ((lane & 3) >> 1);
-    return (uint32_t)(h * 4 * O::NREAD * CROW + k * CROW + 64 * (q ^ k) + 16 * j + 8 * (lane & 1));
+    return (uint32_t)(h * 4 * O::NREAD * ROWB + k * ROWB + 64 * (q ^ k) + 16 * j + 8 * (lane & 1));
 }
 
 // ---------------------------------------------------------------- epilogue
@@ -459,22 +459,22 @@ struct AccSet {
 // ---------------------------------------------------------------- kernel
 
 // Position of the n-th fragment of wave W that is also needed rotated, and their count.
-template <int W>
+template <typename S>
 constexpr int rot_index(int n)
 {
     int c = 0;
-    for (int x = 0; x < Spec<W>::NF; ++x)
-        if (Spec<W>::ROT[x]) {
+    for (int x = 0; x < S::NF; ++x)
+        if (S::ROT[x]) {
             if (c == n) return x;
             ++c;
         }
     return -1;
 }
-template <int W>
+template <typename S>
 constexpr int rot_count()
 {
     int c = 0;
-    for (int x = 0; x < Spec<W>::NF; ++x) c += Spec<W>::ROT[x] ? 1 : 0;
+    for (int x = 0; x < S::NF; ++x) c += S::ROT[x] ? 1 : 0;
     return c;
 }
 
@@ -483,11 +483,10 @@ constexpr int rot_count()
 // work that runs while the matrix cores are busy), then the imaginary parts.  `early` (copy
 // issue) runs after the first MFMA and `mid` (more vector work) after the second
 // imaginary-part MFMA.  The scheduling barriers keep this order.
-template <int ACC, int W, typename Early, typename Mid>
-__device__ __forceinline__ void mma_step(const Frag<4> (&A)[Spec<W>::NF], AccSet<ACC> &acc, Early &&early, Mid &&mid)
+template <int ACC, typename S, typename Early, typename Mid>
+__device__ __forceinline__ void mma_step(const Frag<4> (&A)[S::NF], AccSet<ACC> &acc, Early &&early, Mid &&mid)
 {
-    using S = Spec<W>;
-    constexpr int NROT = rot_count<W>();
+    constexpr int NROT = rot_count<S>();
     static_assert(NROT <= S::NB, "rotations ride on the real-part MFMAs");
     Frag<4> Rt[S::NF];
     static_for<S::NB>([&](auto B) __attribute__((always_inline)) {
@@ -495,7 +494,7 @@ __device__ __forceinline__ void mma_step(const Frag<4> (&A)[Spec<W>::NF], AccSet
         mma(acc.re[b], A[S::BR[b]], A[S::BC[b]]);
         if constexpr (b == 0) early();
         if constexpr (b < NROT) {
-            constexpr int x = rot_index<W>(b);
+            constexpr int x = rot_index<S>(b);
             Rt[x] = op_rot<ACC, !S::ROWROT>(A[x]);
         }
         __builtin_amdgcn_sched_barrier(0);
@@ -509,13 +508,13 @@ __device__ __forceinline__ void mma_step(const Frag<4> (&A)[Spec<W>::NF], AccSet
     });
 }
 
-// Transposing reads of the raw fragments wave W needs at K-step KSTEP.
-template <int ACC, int W, int KSTEP>
-__device__ __forceinline__ void read_step(const uint32_t (&lv)[4], Raw<ACC> (&r)[Spec<W>::NF])
+// Transposing reads of the raw fragments of work list S at K-step KSTEP (rows of ROWB bytes).
+template <int ACC, typename S, int KSTEP, int ROWB = CROW>
+__device__ __forceinline__ void read_step(const uint32_t (&lv)[4], Raw<ACC> (&r)[S::NF])
 {
-    static_for<Spec<W>::NF>([&](auto X) __attribute__((always_inline)) {
+    static_for<S::NF>([&](auto X) __attribute__((always_inline)) {
         constexpr int x = decltype(X)::value;
-        r[x] = read_frag<ACC, Spec<W>::F[x], KSTEP>(lv);
+        r[x] = read_frag<ACC, S::F[x], KSTEP, ROWB>(lv);
     });
 }
 
@@ -523,31 +522,41 @@ __device__ __forceinline__ void read_step(const uint32_t (&lv)[4], Raw<ACC> (&r)
 // are issued before the MFMAs of K-step k, so that a wave keeps its matrix core busy while
 // the other wave of its SIMD waits at the barrier.  copy(k) issues the copies due at
 // K-step k.
-template <int ACC, int W, int NKS, typename Copy>
-__device__ __forceinline__ void block_raw(const uint32_t (&lv)[4], AccSet<ACC> &acc, Copy &&copy)
+template <int ACC, typename S, int NKS, int ROWB = CROW, typename Copy, typename Mid, typename Pre>
+__device__ __forceinline__ void block_raw(const uint32_t (&lv)[4], AccSet<ACC> &acc, Copy &&copy, Mid &&mid, Pre &&pre)
 {
-    using S = Spec<W>;
     Raw<ACC> ra[S::NF], rb[S::NF];
-    read_step<ACC, W, 0>(lv, ra);
+    read_step<ACC, S, 0, ROWB>(lv, ra);
     static_for<NKS>([&](auto K) __attribute__((always_inline)) {
         constexpr int k = decltype(K)::value;
         Raw<ACC>(&cur)[S::NF] = (k & 1) ? rb : ra;
         Raw<ACC>(&nxt)[S::NF] = (k & 1) ? ra : rb;
-        if constexpr (k + 1 < NKS) read_step<ACC, W, k + 1>(lv, nxt);
+        pre(K);
+        if constexpr (k + 1 < NKS) read_step<ACC, S, k + 1, ROWB>(lv, nxt);
         __builtin_amdgcn_sched_barrier(0);
         Frag<4> A[S::NF];
         static_for<S::NF>([&](auto X) __attribute__((always_inline)) {
             constexpr int x = decltype(X)::value;
             A[x] = op_plain<ACC>(cur[x]);
         });
-        mma_step<ACC, W>(A, acc, [&]() __attribute__((always_inline)) { copy(K); }, [] {});
+        mma_step<ACC, S>(A, acc, [&]() __attribute__((always_inline)) { copy(K); },
+                         [&]() __attribute__((always_inline)) { mid(K); });
     });
 }
 
-template <int ACC, int W>
-__device__ __forceinline__ void store_all(const XJob &p, int f, int lane, AccSet<ACC> &acc)
+// Stores of work list S.  Fragment rows F < 8 start at input row_base + 32 F, rows F >= 8
+// (the column segment of a rectangle piece) at col_base + 32 (F - 8); the whole-channel
+// kernel passes zero for both.
+template <typename S>
+__device__ __forceinline__ int frag_row0(int x, int row_base, int col_base)
 {
-    using S = Spec<W>;
+    return S::F[x] >= 8 ? col_base + 32 * (S::F[x] - 8) : row_base + 32 * S::F[x];
+}
+
+template <int ACC, typename S>
+__device__ __forceinline__ void store_all(const XJob &p, int f, int lane, AccSet<ACC> &acc, int row_base = 0,
+                                          int col_base = 0)
+{
     // Opaque copies: the validity masks of the stores depend only on the lane and the array
     // shape, and would otherwise be hoisted out of the channel loop as hundreds of live
     // scalar lane masks.
@@ -557,20 +566,21 @@ __device__ __forceinline__ void store_all(const XJob &p, int f, int lane, AccSet
         static_for<S::NPAIR>([&](auto P) __attribute__((always_inline)) {
             constexpr int b = S::PAIR[decltype(P)::value];
             static_assert(S::BR[b] == S::BR[b + 1] && S::F[S::BC[b + 1]] == S::F[S::BC[b]] + 1, "adjacent pair");
-            store_pair<ACC>(p.out, nin, f, 32 * S::F[S::BR[b]], 32 * S::F[S::BC[b]], l, acc.re[b], acc.im[b],
-                            acc.re[b + 1], acc.im[b + 1]);
+            store_pair<ACC>(p.out, nin, f, frag_row0<S>(S::BR[b], row_base, col_base),
+                            frag_row0<S>(S::BC[b], row_base, col_base), l, acc.re[b], acc.im[b], acc.re[b + 1],
+                            acc.im[b + 1]);
         });
         if constexpr (S::SINGLE >= 0) {
             constexpr int b = S::SINGLE;
-            store_block<ACC>(p.out, nin, npol, accumulate, f, 32 * S::F[S::BR[b]], 32 * S::F[S::BC[b]], l, acc.re[b],
-                             acc.im[b]);
+            store_block<ACC>(p.out, nin, npol, accumulate, f, frag_row0<S>(S::BR[b], row_base, col_base),
+                             frag_row0<S>(S::BC[b], row_base, col_base), l, acc.re[b], acc.im[b]);
         }
         return;
     }
     static_for<S::NB>([&](auto B) __attribute__((always_inline)) {
         constexpr int b = decltype(B)::value;
-        store_block<ACC>(p.out, nin, npol, accumulate, f, 32 * S::F[S::BR[b]], 32 * S::F[S::BC[b]], l, acc.re[b],
-                         acc.im[b]);
+        store_block<ACC>(p.out, nin, npol, accumulate, f, frag_row0<S>(S::BR[b], row_base, col_base),
+                         frag_row0<S>(S::BC[b], row_base, col_base), l, acc.re[b], acc.im[b]);
     });
 }
 
@@ -580,12 +590,12 @@ typedef __attribute__((address_space(3))) u32x4 lds_u4;
 
 // Staged fp16 fragment of block row R for K-step KSTEP at lvf + 8192 KSTEP + 512 R (lvf:
 // this lane's unit of the buffer, see run_wave).
-template <int W, int KSTEP>
-__device__ __forceinline__ void read_staged(uint32_t lvf, Frag<4> (&A)[Spec<W>::NF])
+template <typename S, int KSTEP>
+__device__ __forceinline__ void read_staged(uint32_t lvf, Frag<4> (&A)[S::NF])
 {
-    static_for<Spec<W>::NF>([&](auto X) __attribute__((always_inline)) {
+    static_for<S::NF>([&](auto X) __attribute__((always_inline)) {
         constexpr int x = decltype(X)::value;
-        const u32x4 v = *(const lds_u4 *)(uintptr_t)(lvf + (uint32_t)(KSTEP * 8192 + Spec<W>::F[x] * 512));
+        const u32x4 v = *(const lds_u4 *)(uintptr_t)(lvf + (uint32_t)(KSTEP * 8192 + S::F[x] * 512));
         A[x].w[0] = v[0]; A[x].w[1] = v[1]; A[x].w[2] = v[2]; A[x].w[3] = v[3];
     });
 }
@@ -634,7 +644,7 @@ __device__ __forceinline__ void run_wave(const XJob &p, int lane)
         acc.im[x] = (typename O::acc_t){};
     }
     auto finish_item = [&](Cursor<TB> &cc) __attribute__((always_inline)) {
-        store_all<ACC, W>(p, cc.f, lane, acc);
+        store_all<ACC, Spec<W>>(p, cc.f, lane, acc);
 #pragma unroll
         for (int x = 0; x < MAXB; ++x) {
             acc.re[x] = (typename O::acc_t){};
@@ -673,7 +683,8 @@ __device__ __forceinline__ void run_wave(const XJob &p, int lane)
             uint32_t lv[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) lv[q] = lb[q] + slot * G::BLK;
-            block_raw<ACC, W, NKS>(lv, acc, [&](auto K) __attribute__((always_inline)) { copy_at(K, rs, dst); });
+            block_raw<ACC, Spec<W>, NKS>(lv, acc, [&](auto K) __attribute__((always_inline)) { copy_at(K, rs, dst); },
+                                         [](auto) {}, [](auto) {});
             slot = slot == RING - 1 ? 0 : slot + 1;
 
             if (++cc.blk == cc.nblk) {
@@ -746,7 +757,7 @@ __device__ __forceinline__ void run_wave(const XJob &p, int lane)
             {
                 using S = Spec<W>;
                 Frag<4> fa[S::NF], fbk[S::NF];
-                read_staged<W, 0>(lvf, fa);
+                read_staged<S, 0>(lvf, fa);
                 static_for<NKS>([&](auto K) __attribute__((always_inline)) {
                     constexpr int k = decltype(K)::value;
                     Frag<4>(&cur)[S::NF] = (k & 1) ? fbk : fa;
@@ -756,9 +767,9 @@ __device__ __forceinline__ void run_wave(const XJob &p, int lane)
                         cv0 = convert_read(2 * k, csrc);
                         cv1 = convert_read(2 * k + 1, csrc);
                     }
-                    if constexpr (k + 1 < NKS) read_staged<W, k + 1>(lvf, nxt);
+                    if constexpr (k + 1 < NKS) read_staged<S, k + 1>(lvf, nxt);
                     __builtin_amdgcn_sched_barrier(0);
-                    mma_step<ACC, W>(cur, acc, [&]() __attribute__((always_inline)) { copy_at(K, rs, dst); },
+                    mma_step<ACC, S>(cur, acc, [&]() __attribute__((always_inline)) { copy_at(K, rs, dst); },
                                      [&]() __attribute__((always_inline)) {
                                          if constexpr (W < CW) {
                                              convert_write(2 * k, cv0, cdst);
@@ -802,6 +813,298 @@ __global__ __launch_bounds__(CT, 1) void xeng_chan_kernel(XJob p)
     }
 }
 
+
+// ---------------------------------------------------------------- super-tiles
+
+// Arrays of 256 S inputs (S >= 2) with 4-bit samples on the int8 matrix cores.  A
+// channel's triangle is cut into S diagonal triangles of 256 inputs (the 36-block work
+// lists above) and S (S - 1) rectangles of 256 row inputs x 128 column inputs (32 blocks,
+// one 2x2 square per wave), run as two launches (one work list per kernel).  An item is
+// (window, channel, piece), and the pieces of a channel go to workgroups of one XCD, whose
+// L2 serves the rows they share.  Per block of
+// SP_TB time rows, the piece's input segments (256 row inputs and, for a rectangle, 128
+// column inputs) are copied into a raw ring (one byte per sample), then widened once into
+// the layout the int8 path reads (two bytes per sample, 16-byte chunks XOR-swizzled by
+// row), with both components scaled by 8, exactly: 8 re = ((b & 0xF0) >> 1) | (b & 0x80)
+// per byte, and the same for the low nibble moved up.  The products carry a factor 64,
+// divided out exactly before the stores (the planner keeps such jobs to one window of
+// floor((2^31 - 1) / (128 m^2)) samples).
+
+constexpr int SP_TB = 32, SP_RING = 5;
+constexpr int SP_AROW = 256, SP_BROW = 128;          // raw bytes per time row of the two segments
+constexpr int SP_RAW = SP_TB * (SP_AROW + SP_BROW);   // raw bytes per block
+constexpr int SP_CROW = 768;                          // widened bytes per time row (384 inputs)
+constexpr int SP_CONV = SP_TB * SP_CROW;              // widened bytes per block
+constexpr int SP_LDS = SP_RING * SP_RAW + 2 * SP_CONV;
+constexpr int SP_NKS = SP_TB / COp<ACC_I8>::KS;       // int8 K-steps per block
+constexpr int SP_DPW = 2;                             // copies per wave per block
+static_assert(SP_NKS == 2, "one copy per K-step");
+
+// Rectangle pieces: wave W takes block rows {2 (W/2), 2 (W/2) + 1} and the column blocks
+// {2 (W%2), 2 (W%2) + 1} of the column segment, stored as fragment rows 8..11.
+template <int W>
+struct RectSpec : SquareSpec<(W >> 1), 4 + (W & 1)> {};
+
+// Position in the work of a workgroup: item g = step * grid + pos, pos = (b % 8) grid / 8 +
+// b / 8 when the grid is a multiple of 8 (consecutive items on one XCD); item
+// g = (window * nchan + channel) * npiece + piece.  All fields are wave-uniform.
+template <int TRI>
+struct SCursor {
+    int64_t step;
+    int pos, blk, nblk, f, t0, t1;
+    int seg_a, seg_b;  // first row input, first column input of the piece
+    bool valid;
+
+    __device__ __forceinline__ void set(const XJob &p, int64_t st)
+    {
+        step = st;
+        blk = 0;
+        const int64_t g = st * p.grid + pos;
+        valid = g < p.nitems;
+        if (valid) {
+            const int ns = p.ntile_side, np = TRI ? ns : ns * (ns - 1);
+            const int piece = (int)(g % np);
+            const int64_t q = g / np;
+            const int w = (int)(q / p.nchan);
+            f = (int)(q - (int64_t)w * p.nchan);
+            t0 = w * p.window;
+            t1 = min(p.ntime, t0 + p.window);
+            nblk = (t1 - t0 + SP_TB - 1) / SP_TB;
+            if (TRI) {
+                seg_a = seg_b = 256 * piece;
+            } else {
+                // piece = 2 (i (i - 1) / 2 + j) + h for super-rows j < i, half h
+                const int h = piece & 1;
+                int pr = piece >> 1, i = 1;
+                while (pr >= i) {
+                    pr -= i;
+                    ++i;
+                }
+                seg_a = 256 * i;
+                seg_b = 256 * pr + 128 * h;
+            }
+        } else {  // past the end: empty blocks
+            f = 0;
+            t0 = t1 = 0;
+            nblk = 1;
+            seg_a = seg_b = 0;
+        }
+    }
+    __device__ __forceinline__ void init(const XJob &p)
+    {
+        const int b = blockIdx.x, G = (int)p.grid;
+        pos = (G % 8 == 0) ? (b % 8) * (G / 8) + b / 8 : b;
+        set(p, 0);
+    }
+    __device__ __forceinline__ void next(const XJob &p)
+    {
+        if (++blk == nblk) set(p, step + 1);
+    }
+};
+
+// Descriptor of one input segment of the block the cursor points at (bytes `len` of each
+// row from input `first`); len 0 reads zeros.
+template <typename C>
+__device__ __forceinline__ i32x4s seg_rsrc(const XJob &p, const C &c, int first, int len, uint64_t row_stride)
+{
+    const int r0 = c.t0 + c.blk * SP_TB;
+    const int nrows = len ? max(0, min(SP_TB, c.t1 - r0)) : 0;
+    const uint64_t base = (uint64_t)p.in + ((uint64_t)r0 * p.nchan + c.f) * (uint64_t)p.nin + first;
+    const uint32_t nrec = nrows ? (uint32_t)((nrows - 1) * row_stride + len) : 0u;
+    i32x4s r;
+    r[0] = __builtin_amdgcn_readfirstlane((int)(uint32_t)base);
+    r[1] = __builtin_amdgcn_readfirstlane((int)((uint32_t)(base >> 32) & 0xFFFFu));
+    r[2] = __builtin_amdgcn_readfirstlane((int)nrec);
+    r[3] = 0x00020000;
+    return r;
+}
+
+// Four 4-bit complex samples (one per byte: re high nibble, im low) -> two words of
+// (8 re, 8 im) int8 pairs.
+__device__ __forceinline__ void ci4x4_to_i8x8(uint32_t w, uint32_t &lo, uint32_t &hi)
+{
+    const uint32_t t = w & 0xF0F0F0F0u;
+    const uint32_t re = (t >> 1) | (t & 0x80808080u);
+    const uint32_t u = (w << 4) & 0xF0F0F0F0u;
+    const uint32_t im = (u >> 1) | (u & 0x80808080u);
+    lo = __builtin_amdgcn_perm(im, re, 0x05010400u);
+    hi = __builtin_amdgcn_perm(im, re, 0x07030602u);
+}
+
+template <typename S>
+__device__ __forceinline__ void descale_store(const XJob &p, int f, int lane, AccSet<ACC_I8> &acc, int row_base,
+                                              int col_base)
+{
+#pragma unroll
+    for (int x = 0; x < S::NB; ++x) {
+        acc.re[x] = acc.re[x] >> 6;
+        acc.im[x] = acc.im[x] >> 6;
+    }
+    store_all<ACC_I8, S>(p, f, lane, acc, row_base, col_base);
+}
+
+template <int TRI, int W>
+__device__ __forceinline__ void run_wave_super(const XJob &p, int lane)
+{
+    constexpr int ACC = ACC_I8, RING = SP_RING, DPW = SP_DPW, NKS = SP_NKS;
+    using S = typename std::conditional<TRI != 0, Spec<W>, RectSpec<W>>::type;
+    constexpr int NU = TRI ? 2 : 3;    // widening instructions per wave per block
+    constexpr int NCH = TRI ? 32 : 48; // 16-byte chunks of a widened row
+    const uint64_t row_stride = (uint64_t)p.nchan * p.nin;
+    const uint32_t lds0 = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) uint8_t *)chan_lds;
+    const uint32_t conv0 = lds0 + RING * SP_RAW;
+
+    // copies: instruction A of wave W fills segment-A rows 4W .. 4W + 3 (16 chunks each),
+    // instruction B of waves W and W + 4 the segment-B rows 8 (W % 4) .. + 7 (8 chunks each;
+    // both waves write the same bytes)
+    const int wb = W & 3;
+    const uint32_t voff_a = (uint32_t)((4 * W + (lane >> 4)) * row_stride + 16 * (lane & 15));
+    const uint32_t voff_b = (uint32_t)((8 * wb + (lane >> 3)) * row_stride + 16 * (lane & 7));
+    auto issue = [&](const SCursor<TRI> &c, int slot, int m) __attribute__((always_inline)) {
+        const uint32_t sb = lds0 + slot * SP_RAW;
+        if (m == 0) dma16(seg_rsrc(p, c, c.seg_a, SP_AROW, row_stride), sb + 4 * W * SP_AROW, voff_a);
+        else dma16(seg_rsrc(p, c, c.seg_b, TRI ? 0 : SP_BROW, row_stride), sb + SP_TB * SP_AROW + 8 * wb * SP_BROW,
+                   voff_b);
+    };
+
+    // widening units: instruction m < NU of wave W covers unit U = 512 m + 64 W + lane, row
+    // U / NCH, chunk U % NCH (chunks 0..31 from segment A, 32..47 from segment B)
+    static_assert(NU * 512 == SP_TB * NCH, "units cover the block");
+    uint32_t usrc[NU], udst[NU];
+#pragma unroll
+    for (int m = 0; m < NU; ++m) {
+        const int U = 512 * m + 64 * W + lane;
+        const int row = U / NCH, c = U - NCH * (U / NCH);
+        usrc[m] = (uint32_t)(c < 32 ? row * SP_AROW + 8 * c : SP_TB * SP_AROW + row * SP_BROW + 8 * (c - 32));
+        udst[m] = (uint32_t)(row * SP_CROW + 16 * (c ^ (4 * (row & 3))));
+    }
+    typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+    typedef __attribute__((address_space(3))) u32x2 lds_u2;
+    auto widen = [&](u32x2 v, uint32_t dst) __attribute__((always_inline)) {
+        uint32_t o0, o1, o2, o3;
+        ci4x4_to_i8x8(v[0], o0, o1);
+        ci4x4_to_i8x8(v[1], o2, o3);
+        *(lds_u4 *)(uintptr_t)dst = (u32x4){o0, o1, o2, o3};
+    };
+    auto raw_read = [&](uint32_t a) __attribute__((always_inline)) { return *(const lds_u2 *)(uintptr_t)a; };
+    // the whole widening of one block (prologue)
+    auto widen_block = [&](uint32_t src, uint32_t dst) __attribute__((always_inline)) {
+#pragma unroll
+        for (int m = 0; m < NU; ++m) widen(raw_read(src + usrc[m]), dst + udst[m]);
+    };
+
+    uint32_t lb[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) lb[q] = conv0 + lane_base<ACC, SP_CROW>(lane, q);
+
+    AccSet<ACC> acc;
+#pragma unroll
+    for (int x = 0; x < MAXB; ++x) {
+        acc.re[x] = (i32x16){};
+        acc.im[x] = (i32x16){};
+    }
+
+    SCursor<TRI> dc, nc, cc;
+    dc.init(p);
+    cc.init(p);
+    nc.init(p);
+#pragma unroll
+    for (int d = 0; d < RING - 1; ++d) {
+        issue(dc, d, 0);
+        issue(dc, d, 1);
+        dc.next(p);
+    }
+    nc.next(p);  // the block after cc's
+
+    wait_vm<(RING - 2) * DPW>();
+    __syncthreads();
+    widen_block(lds0, conv0);
+    int slot = 0, fb = 0, ready = 0;
+    while (cc.valid) {
+        // the copy of the next block (own, then everyone's) and the widening of this one
+        // are complete; the raw slot of the previous block and the other buffer are free
+        if (ready == 0) wait_vm<(RING - 3) * DPW>();
+        else --ready;
+        __syncthreads();
+        const SCursor<TRI> ic = dc;
+        const int dslot = slot == 0 ? RING - 1 : slot - 1;
+        dc.next(p);
+        const uint32_t csrc = lds0 + (slot == RING - 1 ? 0 : slot + 1) * SP_RAW;
+        const uint32_t cdst = conv0 + (fb ^ 1) * SP_CONV;
+        uint32_t lv[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) lv[q] = lb[q] + fb * SP_CONV;
+        // K-step k: copy k of the block RING - 1 ahead; widening of the next block: units
+        // read before the MFMAs, widened and stored between them (K-step 0: unit 0 and, for
+        // a rectangle, unit 2; K-step 1: unit 1)
+        u32x2 r0 = {0u, 0u}, r1 = {0u, 0u};
+        auto copy = [&](auto K) __attribute__((always_inline)) { issue(ic, dslot, decltype(K)::value); };
+        auto pre = [&](auto K) __attribute__((always_inline)) {
+            constexpr int k = decltype(K)::value;
+            r0 = raw_read(csrc + usrc[k]);
+            if constexpr (k == 0 && NU == 3) r1 = raw_read(csrc + usrc[2]);
+        };
+        auto mid = [&](auto K) __attribute__((always_inline)) {
+            constexpr int k = decltype(K)::value;
+            widen(r0, cdst + udst[k]);
+            if constexpr (k == 0 && NU == 3) widen(r1, cdst + udst[2]);
+        };
+        block_raw<ACC, S, NKS, SP_CROW>(lv, acc, copy, mid, pre);
+        slot = slot == RING - 1 ? 0 : slot + 1;
+        fb ^= 1;
+        nc.next(p);
+
+        if (++cc.blk == cc.nblk) {
+            wait_vm<0>();
+            ready = RING - 2;
+            descale_store<S>(p, cc.f, lane, acc, cc.seg_a, cc.seg_b);
+#pragma unroll
+            for (int x = 0; x < MAXB; ++x) {
+                acc.re[x] = (i32x16){};
+                acc.im[x] = (i32x16){};
+            }
+            cc.set(p, cc.step + 1);
+        }
+    }
+    // no copy into LDS may outlive the workgroup
+    wait_vm<0>();
+}
+
+template <int TRI>
+__global__ __launch_bounds__(CT, 1) void xeng_super_kernel(XJob p)
+{
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    switch (wave) {
+    case 0: run_wave_super<TRI, 0>(p, lane); break;
+    case 1: run_wave_super<TRI, 1>(p, lane); break;
+    case 2: run_wave_super<TRI, 2>(p, lane); break;
+    case 3: run_wave_super<TRI, 3>(p, lane); break;
+    case 4: run_wave_super<TRI, 4>(p, lane); break;
+    case 5: run_wave_super<TRI, 5>(p, lane); break;
+    case 6: run_wave_super<TRI, 6>(p, lane); break;
+    default: run_wave_super<TRI, 7>(p, lane); break;
+    }
+}
+
+template <int TRI>
+int launch_super_kind(XJob job, int cus, hipStream_t stream)
+{
+    static int done = 0;
+    if (!done) {
+        const hipError_t e = hipFuncSetAttribute((const void *)xeng_super_kernel<TRI>,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, SP_LDS);
+        if (e != hipSuccess) return (int)e;
+        done = 1;
+    }
+    const int ns = job.ntile_side;
+    job.nitems = (int64_t)job.nwindows * job.nchan * (TRI ? ns : ns * (ns - 1));
+    job.grid = job.nitems < cus ? job.nitems : cus;
+    if (job.grid <= 0) return 0;
+    hipLaunchKernelGGL(xeng_super_kernel<TRI>, dim3((unsigned)job.grid), dim3(CT), SP_LDS, stream, job);
+    return (int)hipGetLastError();
+}
+
 // Dynamic LDS beyond the default limit, set once per kernel (one flag per path).
 template <int ACC>
 int allow_lds_chan()
@@ -826,6 +1129,14 @@ int launch_chan_acc(const XJob &job, hipStream_t stream)
 }
 
 }  // namespace
+
+// Both launches of a super-tiled job (triangles, then rectangles); each sets its own item
+// count and grid (at most one workgroup per compute unit, `cus`).
+int launch_super(const XJob &job, int cus, hipStream_t stream)
+{
+    if (int e = launch_super_kind<1>(job, cus, stream)) return e;
+    return launch_super_kind<0>(job, cus, stream);
+}
 
 int launch_chan(const XJob &job, int acc, hipStream_t stream)
 {

@@ -97,9 +97,10 @@ def test_plan_sizes_config_shapes():
     p = X.xcorr_plan(128, 2, 1024, 1000, X.IN_CI8, X.ACC_F16_MMA_F32, 18, 128)
     assert (p["tile"], p["ntile_side"], p["tiles_per_chan"], p["nitems"]) == (128, 2, 3, 3072)
     assert p["computed_cmacs"] == 36 * 1024 * 1024 * 1000
-    # 512 stations x 2 pol, 4-bit: 36 tiles per channel
+    # 512 stations x 2 pol, 4-bit: 16 super-tile pieces per channel (36 tiles of 128)
     p = X.xcorr_plan(512, 2, 256, 4096, X.IN_CI4, X.ACC_I8_MMA_I32, 0)
-    assert p["tiles_per_chan"] == 36 and p["nwindows"] == 1 and p["out_dtype"] == X.OUT_CI32
+    assert p["tiles_per_chan"] == 16 and p["nwindows"] == 1 and p["out_dtype"] == X.OUT_CI32
+    assert X.xcorr_plan(512, 2, 256, 4096, X.IN_CI4, X.ACC_I8_MMA_I32, 0, 128)["tiles_per_chan"] == 36
     assert p["in_bytes"] == 4096 * 256 * 1024
 
 
@@ -188,6 +189,10 @@ def test_tile_choice(acc):
     assert tile(129, 2) == 128        # nin 258
     assert tile(128, 2, fmt=X.IN_CI4) == 128
     assert tile(128, 2, a=X.ACC_F32_CMAC) == 64
+    # 4-bit samples from 512 inputs (a multiple of 256): super-tiles on the int8 path
+    assert tile(256, 2, fmt=X.IN_CI4) == (512 if acc == X.ACC_I8_MMA_I32 else 128)
+    assert tile(512, 2, fmt=X.IN_CI4) == (512 if acc == X.ACC_I8_MMA_I32 else 128)
+    assert tile(260, 2, fmt=X.IN_CI4) == 128
     # explicit shapes
     assert tile(32, 2, 256) == 256    # allowed below the automatic threshold
     assert tile(128, 2, 128) == 128
@@ -211,3 +216,34 @@ def test_whole_channel_items_and_windows():
     assert p["nitems"] == 10 * 2 and p["out_dtype"] == X.OUT_CI64
     p = X.xcorr_plan(16, 2, 10, 100, X.IN_CI8, X.ACC_F16_MMA_F32, 0, 256)
     assert p["computed_cmacs"] == 36 * 1024 * 10 * 100
+
+
+def test_super_tile_plan():
+    # 1024 inputs, 4-bit samples, int8 path: 4 super-rows -> 4 triangles + 12 rectangles
+    p = X.xcorr_plan(512, 2, 256, 4096, X.IN_CI4, X.ACC_I8_MMA_I32, 0, 512)
+    assert p["tile"] == 512 and p["ntile_side"] == 4 and p["tiles_per_chan"] == 16
+    assert p["nwindows"] == 1 and p["out_dtype"] == X.OUT_CI32
+    assert p["nitems"] == 256 * 16
+    # computed pairs: 4 x 36 blocks + 12 x 32 blocks of 32 x 32
+    assert p["computed_cmacs"] == (4 * 36 + 12 * 32) * 1024 * 256 * 4096
+    assert p["useful_cmacs"] == 1024 * 1025 // 2 * 256 * 4096
+    # the operands are 8 x the samples: one window of floor((2^31-1) / (128 m^2)) samples
+    lim = (2 ** 31 - 1) // (128 * 8 * 8)
+    X.xcorr_plan(256, 2, 2, lim, X.IN_CI4, X.ACC_I8_MMA_I32, 0, 512)
+    with pytest.raises(X.XcorrError):
+        X.xcorr_plan(256, 2, 2, lim + 1, X.IN_CI4, X.ACC_I8_MMA_I32, 0, 512)
+    # a smaller declared bound allows longer jobs
+    X.xcorr_plan(256, 2, 2, lim + 1, X.IN_CI4, X.ACC_I8_MMA_I32, 4, 512)
+
+
+@pytest.mark.parametrize("args", [
+    (128, 2, 4, 100, "IN_CI4", "ACC_I8_MMA_I32"),   # 256 inputs: below 512
+    (200, 2, 4, 100, "IN_CI4", "ACC_I8_MMA_I32"),   # 400 inputs: not a multiple of 256
+    (1280, 2, 4, 100, "IN_CI4", "ACC_I8_MMA_I32"),  # 2560 inputs: above 2048
+    (256, 2, 4, 100, "IN_CI8", "ACC_I8_MMA_I32"),   # 8-bit samples
+    (256, 2, 4, 100, "IN_CI4", "ACC_F8E4M3_MMA_F32"),  # fp8 path
+])
+def test_super_tile_rejected(args):
+    ns, npol, F, T, fmt, acc = args
+    with pytest.raises(X.XcorrError):
+        X.xcorr_plan(ns, npol, F, T, getattr(X, fmt), getattr(X, acc), 0, 512)

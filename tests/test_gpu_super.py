@@ -1,0 +1,80 @@
+"""GPU parity of the super-tiled kernel (tile 512: 4-bit samples on the int8 matrix cores,
+each channel cut into 256-input triangles and 256 x 128 rectangles, operands widened to
+8 x the samples in LDS) against the oracle, bit for bit."""
+
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from paper_1107_4264_amd import synth
+from tests.gpu_util import as_exact_int, run_xeng, say
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [
+    # (nstation, npol, nchan, ntime)
+    (256, 2, 3, 100),    # 512 inputs: 2 triangles + 2 rectangles; last time block partial
+    (384, 2, 2, 77),     # 768 inputs: 3 triangles + 6 rectangles
+    (512, 2, 2, 70),     # 1024 inputs: 4 triangles + 12 rectangles
+    (512, 1, 2, 33),     # single polarisation: the generic store path
+    (256, 2, 2, 1),      # a single sample
+    (256, 2, 1, 32),     # exactly one block
+]
+
+
+def _check(got, want, label):
+    g = as_exact_int(got)
+    if not np.array_equal(g, want):
+        bad = np.argwhere(g != want)
+        say(label, "MISMATCH count", len(bad), "first", bad[:5].tolist(),
+            "got", g[tuple(bad[0])], "want", want[tuple(bad[0])])
+    assert np.array_equal(g, want), label
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "x".join(map(str, s)))
+def test_super_matches_oracle(oracle_mod, shape):
+    ns, npol, F, T = shape
+    v = synth.voltages_np(synth.SEED_BASE + 60 + ns + T, T, F, ns * npol, ("uniform", -8, 7))
+    packed = synth.pack_ci4(v)
+    say("super", shape)
+    got, _ = run_xeng(packed, ns, npol, "ci4", "i8", tile=512)
+    _check(got, oracle_mod.xcorr(packed, ns, npol, fmt=oracle_mod.CI4), f"super/{shape}")
+
+
+def test_super_extreme_values(oracle_mod):
+    """Full-scale 4-bit samples, some inputs pinned at -8 (the widened operand -64, whose
+    rotation +64 still fits int8)."""
+    ns, npol, F, T = 256, 2, 2, 150
+    v = synth.voltages_np(synth.SEED_BASE + 61, T, F, ns * npol, ("uniform", -8, 7))
+    v[:, :, :6] = -8
+    v[:, :, 300:302] = 7
+    packed = synth.pack_ci4(v)
+    say("super extreme")
+    got, _ = run_xeng(packed, ns, npol, "ci4", "i8", tile=512)
+    _check(got, oracle_mod.xcorr(packed, ns, npol, fmt=oracle_mod.CI4), "super-extreme")
+
+
+# channels sampled from a walk over 150 channels of 512 inputs (4 pieces each, 600 items):
+# first, second and third items of workgroups, and the last channel
+WALK_CHANS = [0, 1, 31, 32, 63, 64, 65, 127, 128, 149]
+
+
+def test_super_many_items_per_workgroup(oracle_mod):
+    ns, npol, F, T = 256, 2, 150, 40
+    v = synth.voltages_np(synth.SEED_BASE + 62, T, F, ns * npol, ("uniform", -8, 7))
+    packed = synth.pack_ci4(v)
+    say("super walk", F)
+    got, _ = run_xeng(packed, ns, npol, "ci4", "i8", tile=512)
+    want = oracle_mod.xcorr(packed, ns, npol, fmt=oracle_mod.CI4, chans=WALK_CHANS)
+    _check(got[WALK_CHANS], want, "super-walk")
+
+
+def test_super_equals_tiles():
+    """Super-tiles and 128-tiles give the same bits."""
+    ns, npol, F, T = 512, 2, 3, 200
+    v = synth.voltages_np(synth.SEED_BASE + 63, T, F, ns * npol, ("uniform", -8, 7))
+    packed = synth.pack_ci4(v)
+    a, _ = run_xeng(packed, ns, npol, "ci4", "i8", tile=512)
+    b, _ = run_xeng(packed, ns, npol, "ci4", "i8", tile=128)
+    assert np.array_equal(a, b)
