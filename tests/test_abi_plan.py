@@ -234,6 +234,9 @@ def test_super_tile_plan():
         X.xcorr_plan(256, 2, 2, lim + 1, X.IN_CI4, X.ACC_I8_MMA_I32, 0, 512)
     # a smaller declared bound allows longer jobs
     X.xcorr_plan(256, 2, 2, lim + 1, X.IN_CI4, X.ACC_I8_MMA_I32, 4, 512)
+    # past the scaled window the automatic choice keeps 128-tiles (same output type)
+    p = X.xcorr_plan(256, 2, 2, lim + 1, X.IN_CI4, X.ACC_I8_MMA_I32, 0)
+    assert p["tile"] == 128 and p["out_dtype"] == X.OUT_CI32
 
 
 @pytest.mark.parametrize("args", [

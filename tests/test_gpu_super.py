@@ -78,3 +78,50 @@ def test_super_equals_tiles():
     a, _ = run_xeng(packed, ns, npol, "ci4", "i8", tile=512)
     b, _ = run_xeng(packed, ns, npol, "ci4", "i8", tile=128)
     assert np.array_equal(a, b)
+
+
+def test_super_stream_accumulates(oracle_mod):
+    """A streaming integration planned on super-tiles adds every chunk into the int64
+    totals (the accumulating stores of the super-tiled kernel)."""
+    import torch
+
+    from paper_1107_4264_amd import xcorr as X
+    from tests.gpu_util import device
+
+    device()
+    ns, npol, F, chunk, nchunk = 256, 2, 2, 50, 3
+    assert X.xcorr_plan(ns, npol, F, chunk, X.IN_CI4, X.ACC_I8_MMA_I32, 0)["tile"] == 512
+    v = synth.voltages_np(synth.SEED_BASE + 64, chunk * nchunk, F, ns * npol, ("uniform", -8, 7))
+    packed = synth.pack_ci4(v)
+    want = oracle_mod.xcorr(packed, ns, npol, fmt=oracle_mod.CI4)
+    st = X.Stream(ns, npol, F, chunk, "ci4", "i8")
+    out = st.begin()
+    for c in range(nchunk):
+        st.push(torch.from_numpy(np.ascontiguousarray(packed[c * chunk:(c + 1) * chunk])).pin_memory())
+    assert st.end() == chunk * nchunk
+    torch.cuda.synchronize()
+    _check(out.cpu().numpy(), want, "super-stream")
+    st.close()
+
+
+def test_super_misaligned_input_falls_back(oracle_mod):
+    """An input pointer off the 16-byte grid runs 128-tiles (the row copies need aligned
+    rows) and still gives the oracle's bits."""
+    import torch
+
+    from paper_1107_4264_amd import xcorr as X
+    from tests.gpu_util import device
+
+    dev = device()
+    ns, npol, F, T = 256, 2, 2, 40
+    v = synth.voltages_np(synth.SEED_BASE + 65, T, F, ns * npol, ("uniform", -8, 7))
+    packed = synth.pack_ci4(v)
+    flat = torch.zeros(packed.size + 16, dtype=torch.uint8, device=dev)
+    flat[3:3 + packed.size] = torch.from_numpy(packed.reshape(-1)).to(dev)
+    xin = flat[3:3 + packed.size].view(packed.shape)
+    assert xin.data_ptr() % 16 == 3
+    c = X.Correlator(ns, npol, F, T, "ci4", "i8", tile=512)
+    out = c.run(xin)
+    torch.cuda.synchronize()
+    _check(out.cpu().numpy(), oracle_mod.xcorr(packed, ns, npol, fmt=oracle_mod.CI4), "super-misaligned")
+    c.close()
