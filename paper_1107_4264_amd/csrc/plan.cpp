@@ -77,9 +77,13 @@ bool chan_kernel_ok(int nin, int in_fmt, int acc)
 
 bool super_kernel_ok(int nin, int nchan, int64_t ntime, int in_fmt, int acc, int max_abs)
 {
-    if (in_fmt != IN_CI4 || acc != ACC_I8 || nin % 256 != 0 || nin < 512 || nin > 2048) return false;
+    if (in_fmt != IN_CI4 || (acc != ACC_I8 && acc != ACC_F8) || nin % 256 != 0 || nin < 512 || nin > 2048)
+        return false;
     // the copy offsets of a block (32 rows) stay below 2^32 bytes
     if (32 * (int64_t)nchan * nin >= ((int64_t)1 << 32)) return false;
+    // fp8 operands are the samples themselves (the usual fp32 windows); int8 operands are
+    // 8 x the samples, so the whole job must fit one int32 window of the scaled sums
+    if (acc == ACC_F8) return true;
     const int64_t m = max_abs;
     return m >= 1 && ntime <= (int64_t)2147483647 / (128 * m * m);
 }

@@ -74,15 +74,22 @@ struct Geom {
 
 template <int ACC>
 struct COp;
-// KS: samples per K-step; NREAD: transposing reads per fragment (4 samples each).
+// KS: samples per K-step; NREAD: transposing reads per fragment (4 samples each); FW:
+// 32-bit words of an MFMA operand fragment per lane.
 template <>
 struct COp<ACC_I8> {
-    static constexpr int KS = 16, NREAD = 2;
+    static constexpr int KS = 16, NREAD = 2, FW = 4;
     using acc_t = i32x16;
 };
 template <>
 struct COp<ACC_F16> {
-    static constexpr int KS = 8, NREAD = 1;
+    static constexpr int KS = 8, NREAD = 1, FW = 4;
+    using acc_t = f32x16;
+};
+// fp8 e4m3 (super-tiles only): 32x32x64 MFMAs, 32 samples per K-step
+template <>
+struct COp<ACC_F8> {
+    static constexpr int KS = 32, NREAD = 4, FW = 8;
     using acc_t = f32x16;
 };
 
@@ -122,12 +129,12 @@ __device__ __forceinline__ void f16_pairs(uint32_t w, uint32_t &p0, uint32_t &p1
 }
 
 template <int ACC>
-__device__ __forceinline__ Frag<4> op_plain(const Raw<ACC> &r)
+__device__ __forceinline__ Frag<COp<ACC>::FW> op_plain(const Raw<ACC> &r)
 {
-    Frag<4> o;
-    if constexpr (ACC == ACC_I8) {
+    Frag<COp<ACC>::FW> o;
+    if constexpr (ACC == ACC_I8 || ACC == ACC_F8) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) o.w[k] = r.w[k];
+        for (int k = 0; k < COp<ACC>::FW; ++k) o.w[k] = r.w[k];
     } else {
         f16_pairs(r.w[0], o.w[0], o.w[1]);
         f16_pairs(r.w[1], o.w[2], o.w[3]);
@@ -137,14 +144,18 @@ __device__ __forceinline__ Frag<4> op_plain(const Raw<ACC> &r)
 
 // Rotated operands for the imaginary part, Im V_ij = sum_t (im_i re_j - re_i im_j): either
 // the column operand as (-im, re) pairs (COL) or the row operand as (im, -re) pairs, from the
-// plain operand words (int8 pairs or fp16 pairs), exactly.
+// plain operand words (int8, fp16 or fp8 e4m3 pairs), exactly.
 template <int ACC, bool COL>
-__device__ __forceinline__ Frag<4> op_rot(const Frag<4> &a)
+__device__ __forceinline__ Frag<COp<ACC>::FW> op_rot(const Frag<COp<ACC>::FW> &a)
 {
-    Frag<4> o;
+    Frag<COp<ACC>::FW> o;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        if constexpr (ACC == ACC_I8) {
+    for (int k = 0; k < COp<ACC>::FW; ++k) {
+        if constexpr (ACC == ACC_F8) {
+            // swap the bytes of each pair, then flip the sign bit of the component negated
+            const uint32_t sw = __builtin_amdgcn_perm(a.w[k], a.w[k], 0x02030001u);
+            o.w[k] = sw ^ (COL ? 0x00800080u : 0x80008000u);
+        } else if constexpr (ACC == ACC_I8) {
             if constexpr (COL) {
                 o.w[k] = rotate_pairs<ACC_I8>(a.w[k]);
             } else {
@@ -484,11 +495,12 @@ constexpr int rot_count()
 // issue) runs after the first MFMA and `mid` (more vector work) after the second
 // imaginary-part MFMA.  The scheduling barriers keep this order.
 template <int ACC, typename S, typename Early, typename Mid>
-__device__ __forceinline__ void mma_step(const Frag<4> (&A)[S::NF], AccSet<ACC> &acc, Early &&early, Mid &&mid)
+__device__ __forceinline__ void mma_step(const Frag<COp<ACC>::FW> (&A)[S::NF], AccSet<ACC> &acc, Early &&early,
+                                         Mid &&mid)
 {
     constexpr int NROT = rot_count<S>();
     static_assert(NROT <= S::NB, "rotations ride on the real-part MFMAs");
-    Frag<4> Rt[S::NF];
+    Frag<COp<ACC>::FW> Rt[S::NF];
     static_for<S::NB>([&](auto B) __attribute__((always_inline)) {
         constexpr int b = decltype(B)::value;
         mma(acc.re[b], A[S::BR[b]], A[S::BC[b]]);
@@ -534,7 +546,7 @@ __device__ __forceinline__ void block_raw(const uint32_t (&lv)[4], AccSet<ACC> &
         pre(K);
         if constexpr (k + 1 < NKS) read_step<ACC, S, k + 1, ROWB>(lv, nxt);
         __builtin_amdgcn_sched_barrier(0);
-        Frag<4> A[S::NF];
+        Frag<COp<ACC>::FW> A[S::NF];
         static_for<S::NF>([&](auto X) __attribute__((always_inline)) {
             constexpr int x = decltype(X)::value;
             A[x] = op_plain<ACC>(cur[x]);
@@ -836,9 +848,7 @@ constexpr int SP_RAW = SP_TB * (SP_AROW + SP_BROW);   // raw bytes per block
 constexpr int SP_CROW = 768;                          // widened bytes per time row (384 inputs)
 constexpr int SP_CONV = SP_TB * SP_CROW;              // widened bytes per block
 constexpr int SP_LDS = SP_RING * SP_RAW + 2 * SP_CONV;
-constexpr int SP_NKS = SP_TB / COp<ACC_I8>::KS;       // int8 K-steps per block
 constexpr int SP_DPW = 2;                             // copies per wave per block
-static_assert(SP_NKS == 2, "one copy per K-step");
 
 // Rectangle pieces: wave W takes block rows {2 (W/2), 2 (W/2) + 1} and the column blocks
 // {2 (W%2), 2 (W%2) + 1} of the column segment, stored as fragment rows 8..11.
@@ -921,6 +931,29 @@ __device__ __forceinline__ i32x4s seg_rsrc(const XJob &p, const C &c, int first,
 
 // Four 4-bit complex samples (one per byte: re high nibble, im low) -> two words of
 // (8 re, 8 im) int8 pairs.
+// e4m3 codes of four signed 4-bit values (one per byte, low nibble): two 8-entry byte
+// tables (values 0..7 and -8..-1, indexed by the low three bits) and the sign bit of each
+// nibble spread to a byte mask ((t << 8) - t is 0xFF per byte where t is 1, no carries).
+__device__ __forceinline__ uint32_t nibbles_to_e4m3(uint32_t n)
+{
+    const uint32_t idx = n & 0x07070707u;
+    const uint32_t pos = __builtin_amdgcn_perm(0x4E4C4A48u, 0x44403800u, idx);  // 0, 1, .., 7
+    const uint32_t neg = __builtin_amdgcn_perm(0xB8C0C4C8u, 0xCACCCED0u, idx);  // -8, -7, .., -1
+    const uint32_t t = (n >> 3) & 0x01010101u;
+    const uint32_t m = (t << 8) - t;
+    return (neg & m) | (pos & ~m);
+}
+
+// Four 4-bit complex samples (one per byte: re high nibble, im low) -> two words of
+// (re, im) fp8 e4m3 pairs, exactly.
+__device__ __forceinline__ void ci4x4_to_e4m3x8(uint32_t w, uint32_t &lo, uint32_t &hi)
+{
+    const uint32_t re = nibbles_to_e4m3((w >> 4) & 0x0F0F0F0Fu);
+    const uint32_t im = nibbles_to_e4m3(w & 0x0F0F0F0Fu);
+    lo = __builtin_amdgcn_perm(im, re, 0x05010400u);
+    hi = __builtin_amdgcn_perm(im, re, 0x07030602u);
+}
+
 __device__ __forceinline__ void ci4x4_to_i8x8(uint32_t w, uint32_t &lo, uint32_t &hi)
 {
     const uint32_t t = w & 0xF0F0F0F0u;
@@ -931,22 +964,27 @@ __device__ __forceinline__ void ci4x4_to_i8x8(uint32_t w, uint32_t &lo, uint32_t
     hi = __builtin_amdgcn_perm(im, re, 0x07030602u);
 }
 
-template <typename S>
-__device__ __forceinline__ void descale_store(const XJob &p, int f, int lane, AccSet<ACC_I8> &acc, int row_base,
+// int8: the operands are 8 x the samples, the sums 64 x the visibilities (exact shift)
+template <int ACC, typename S>
+__device__ __forceinline__ void descale_store(const XJob &p, int f, int lane, AccSet<ACC> &acc, int row_base,
                                               int col_base)
 {
+    if constexpr (ACC == ACC_I8) {
 #pragma unroll
-    for (int x = 0; x < S::NB; ++x) {
-        acc.re[x] = acc.re[x] >> 6;
-        acc.im[x] = acc.im[x] >> 6;
+        for (int x = 0; x < S::NB; ++x) {
+            acc.re[x] = acc.re[x] >> 6;
+            acc.im[x] = acc.im[x] >> 6;
+        }
     }
-    store_all<ACC_I8, S>(p, f, lane, acc, row_base, col_base);
+    store_all<ACC, S>(p, f, lane, acc, row_base, col_base);
 }
 
-template <int TRI, int W>
+template <int ACC, int TRI, int W>
 __device__ __forceinline__ void run_wave_super(const XJob &p, int lane)
 {
-    constexpr int ACC = ACC_I8, RING = SP_RING, DPW = SP_DPW, NKS = SP_NKS;
+    constexpr int RING = SP_RING, DPW = SP_DPW, NKS = SP_TB / COp<ACC>::KS;
+    static_assert(NKS >= 1 && SP_TB % COp<ACC>::KS == 0, "whole K-steps per block");
+    using acc_t = typename COp<ACC>::acc_t;
     using S = typename std::conditional<TRI != 0, Spec<W>, RectSpec<W>>::type;
     constexpr int NU = TRI ? 2 : 3;    // widening instructions per wave per block
     constexpr int NCH = TRI ? 32 : 48; // 16-byte chunks of a widened row
@@ -982,8 +1020,13 @@ __device__ __forceinline__ void run_wave_super(const XJob &p, int lane)
     typedef __attribute__((address_space(3))) u32x2 lds_u2;
     auto widen = [&](u32x2 v, uint32_t dst) __attribute__((always_inline)) {
         uint32_t o0, o1, o2, o3;
-        ci4x4_to_i8x8(v[0], o0, o1);
-        ci4x4_to_i8x8(v[1], o2, o3);
+        if constexpr (ACC == ACC_I8) {
+            ci4x4_to_i8x8(v[0], o0, o1);
+            ci4x4_to_i8x8(v[1], o2, o3);
+        } else {
+            ci4x4_to_e4m3x8(v[0], o0, o1);
+            ci4x4_to_e4m3x8(v[1], o2, o3);
+        }
         *(lds_u4 *)(uintptr_t)dst = (u32x4){o0, o1, o2, o3};
     };
     auto raw_read = [&](uint32_t a) __attribute__((always_inline)) { return *(const lds_u2 *)(uintptr_t)a; };
@@ -1000,8 +1043,8 @@ __device__ __forceinline__ void run_wave_super(const XJob &p, int lane)
     AccSet<ACC> acc;
 #pragma unroll
     for (int x = 0; x < MAXB; ++x) {
-        acc.re[x] = (i32x16){};
-        acc.im[x] = (i32x16){};
+        acc.re[x] = (acc_t){};
+        acc.im[x] = (acc_t){};
     }
 
     SCursor<TRI> dc, nc, cc;
@@ -1034,20 +1077,26 @@ __device__ __forceinline__ void run_wave_super(const XJob &p, int lane)
         uint32_t lv[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) lv[q] = lb[q] + fb * SP_CONV;
-        // K-step k: copy k of the block RING - 1 ahead; widening of the next block: units
-        // read before the MFMAs, widened and stored between them (K-step 0: unit 0 and, for
-        // a rectangle, unit 2; K-step 1: unit 1)
-        u32x2 r0 = {0u, 0u}, r1 = {0u, 0u};
-        auto copy = [&](auto K) __attribute__((always_inline)) { issue(ic, dslot, decltype(K)::value); };
+        // K-step k issues copy m (of the block RING - 1 ahead) when m NKS / DPW == k, and
+        // widens unit u of the next block when u NKS / NU == k: the unit is read before the
+        // MFMAs, widened and stored between them
+        u32x2 rr[NU];
+        auto copy = [&](auto K) __attribute__((always_inline)) {
+            static_for<DPW>([&](auto M) __attribute__((always_inline)) {
+                if constexpr (decltype(M)::value * NKS / DPW == decltype(K)::value) issue(ic, dslot, decltype(M)::value);
+            });
+        };
         auto pre = [&](auto K) __attribute__((always_inline)) {
-            constexpr int k = decltype(K)::value;
-            r0 = raw_read(csrc + usrc[k]);
-            if constexpr (k == 0 && NU == 3) r1 = raw_read(csrc + usrc[2]);
+            static_for<NU>([&](auto U) __attribute__((always_inline)) {
+                constexpr int u = decltype(U)::value;
+                if constexpr (u * NKS / NU == decltype(K)::value) rr[u] = raw_read(csrc + usrc[u]);
+            });
         };
         auto mid = [&](auto K) __attribute__((always_inline)) {
-            constexpr int k = decltype(K)::value;
-            widen(r0, cdst + udst[k]);
-            if constexpr (k == 0 && NU == 3) widen(r1, cdst + udst[2]);
+            static_for<NU>([&](auto U) __attribute__((always_inline)) {
+                constexpr int u = decltype(U)::value;
+                if constexpr (u * NKS / NU == decltype(K)::value) widen(rr[u], cdst + udst[u]);
+            });
         };
         block_raw<ACC, S, NKS, SP_CROW>(lv, acc, copy, mid, pre);
         slot = slot == RING - 1 ? 0 : slot + 1;
@@ -1057,11 +1106,11 @@ __device__ __forceinline__ void run_wave_super(const XJob &p, int lane)
         if (++cc.blk == cc.nblk) {
             wait_vm<0>();
             ready = RING - 2;
-            descale_store<S>(p, cc.f, lane, acc, cc.seg_a, cc.seg_b);
+            descale_store<ACC, S>(p, cc.f, lane, acc, cc.seg_a, cc.seg_b);
 #pragma unroll
             for (int x = 0; x < MAXB; ++x) {
-                acc.re[x] = (i32x16){};
-                acc.im[x] = (i32x16){};
+                acc.re[x] = (acc_t){};
+                acc.im[x] = (acc_t){};
             }
             cc.set(p, cc.step + 1);
         }
@@ -1070,29 +1119,29 @@ __device__ __forceinline__ void run_wave_super(const XJob &p, int lane)
     wait_vm<0>();
 }
 
-template <int TRI>
+template <int ACC, int TRI>
 __global__ __launch_bounds__(CT, 1) void xeng_super_kernel(XJob p)
 {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     switch (wave) {
-    case 0: run_wave_super<TRI, 0>(p, lane); break;
-    case 1: run_wave_super<TRI, 1>(p, lane); break;
-    case 2: run_wave_super<TRI, 2>(p, lane); break;
-    case 3: run_wave_super<TRI, 3>(p, lane); break;
-    case 4: run_wave_super<TRI, 4>(p, lane); break;
-    case 5: run_wave_super<TRI, 5>(p, lane); break;
-    case 6: run_wave_super<TRI, 6>(p, lane); break;
-    default: run_wave_super<TRI, 7>(p, lane); break;
+    case 0: run_wave_super<ACC, TRI, 0>(p, lane); break;
+    case 1: run_wave_super<ACC, TRI, 1>(p, lane); break;
+    case 2: run_wave_super<ACC, TRI, 2>(p, lane); break;
+    case 3: run_wave_super<ACC, TRI, 3>(p, lane); break;
+    case 4: run_wave_super<ACC, TRI, 4>(p, lane); break;
+    case 5: run_wave_super<ACC, TRI, 5>(p, lane); break;
+    case 6: run_wave_super<ACC, TRI, 6>(p, lane); break;
+    default: run_wave_super<ACC, TRI, 7>(p, lane); break;
     }
 }
 
-template <int TRI>
+template <int ACC, int TRI>
 int launch_super_kind(XJob job, int cus, hipStream_t stream)
 {
     static int done = 0;
     if (!done) {
-        const hipError_t e = hipFuncSetAttribute((const void *)xeng_super_kernel<TRI>,
+        const hipError_t e = hipFuncSetAttribute((const void *)xeng_super_kernel<ACC, TRI>,
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, SP_LDS);
         if (e != hipSuccess) return (int)e;
         done = 1;
@@ -1101,7 +1150,7 @@ int launch_super_kind(XJob job, int cus, hipStream_t stream)
     job.nitems = (int64_t)job.nwindows * job.nchan * (TRI ? ns : ns * (ns - 1));
     job.grid = job.nitems < cus ? job.nitems : cus;
     if (job.grid <= 0) return 0;
-    hipLaunchKernelGGL(xeng_super_kernel<TRI>, dim3((unsigned)job.grid), dim3(CT), SP_LDS, stream, job);
+    hipLaunchKernelGGL((xeng_super_kernel<ACC, TRI>), dim3((unsigned)job.grid), dim3(CT), SP_LDS, stream, job);
     return (int)hipGetLastError();
 }
 
@@ -1132,10 +1181,17 @@ int launch_chan_acc(const XJob &job, hipStream_t stream)
 
 // Both launches of a super-tiled job (triangles, then rectangles); each sets its own item
 // count and grid (at most one workgroup per compute unit, `cus`).
-int launch_super(const XJob &job, int cus, hipStream_t stream)
+int launch_super(const XJob &job, int acc, int cus, hipStream_t stream)
 {
-    if (int e = launch_super_kind<1>(job, cus, stream)) return e;
-    return launch_super_kind<0>(job, cus, stream);
+    if (acc == ACC_I8) {
+        if (int e = launch_super_kind<ACC_I8, 1>(job, cus, stream)) return e;
+        return launch_super_kind<ACC_I8, 0>(job, cus, stream);
+    }
+    if (acc == ACC_F8) {
+        if (int e = launch_super_kind<ACC_F8, 1>(job, cus, stream)) return e;
+        return launch_super_kind<ACC_F8, 0>(job, cus, stream);
+    }
+    return (int)hipErrorInvalidValue;
 }
 
 int launch_chan(const XJob &job, int acc, hipStream_t stream)

@@ -192,6 +192,7 @@ def test_tile_choice(acc):
     # 4-bit samples from 512 inputs (a multiple of 256): super-tiles on the int8 path
     assert tile(256, 2, fmt=X.IN_CI4) == (512 if acc == X.ACC_I8_MMA_I32 else 128)
     assert tile(512, 2, fmt=X.IN_CI4) == (512 if acc == X.ACC_I8_MMA_I32 else 128)
+    assert tile(512, 2, fmt=X.IN_CI4, a=X.ACC_F8E4M3_MMA_F32) == 512
     assert tile(260, 2, fmt=X.IN_CI4) == 128
     # explicit shapes
     assert tile(32, 2, 256) == 256    # allowed below the automatic threshold
@@ -244,7 +245,7 @@ def test_super_tile_plan():
     (200, 2, 4, 100, "IN_CI4", "ACC_I8_MMA_I32"),   # 400 inputs: not a multiple of 256
     (1280, 2, 4, 100, "IN_CI4", "ACC_I8_MMA_I32"),  # 2560 inputs: above 2048
     (256, 2, 4, 100, "IN_CI8", "ACC_I8_MMA_I32"),   # 8-bit samples
-    (256, 2, 4, 100, "IN_CI4", "ACC_F8E4M3_MMA_F32"),  # fp8 path
+    (256, 2, 4, 100, "IN_CI4", "ACC_F16_MMA_F32"),  # fp16 path
 ])
 def test_super_tile_rejected(args):
     ns, npol, F, T, fmt, acc = args

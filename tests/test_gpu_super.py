@@ -1,6 +1,6 @@
-"""GPU parity of the super-tiled kernel (tile 512: 4-bit samples on the int8 matrix cores,
-each channel cut into 256-input triangles and 256 x 128 rectangles, operands widened to
-8 x the samples in LDS) against the oracle, bit for bit."""
+"""GPU parity of the super-tiled kernel (tile 512: 4-bit samples on the int8 or fp8 matrix
+cores, each channel cut into 256-input triangles and 256 x 128 rectangles, operands widened
+in LDS to 8 x the samples as int8, or to fp8 e4m3) against the oracle, bit for bit."""
 
 from __future__ import annotations
 
@@ -32,17 +32,22 @@ def _check(got, want, label):
     assert np.array_equal(g, want), label
 
 
+ACCS = ["i8", "f8"]
+
+
+@pytest.mark.parametrize("acc", ACCS)
 @pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "x".join(map(str, s)))
-def test_super_matches_oracle(oracle_mod, shape):
+def test_super_matches_oracle(oracle_mod, acc, shape):
     ns, npol, F, T = shape
     v = synth.voltages_np(synth.SEED_BASE + 60 + ns + T, T, F, ns * npol, ("uniform", -8, 7))
     packed = synth.pack_ci4(v)
-    say("super", shape)
-    got, _ = run_xeng(packed, ns, npol, "ci4", "i8", tile=512)
-    _check(got, oracle_mod.xcorr(packed, ns, npol, fmt=oracle_mod.CI4), f"super/{shape}")
+    say("super", acc, shape)
+    got, _ = run_xeng(packed, ns, npol, "ci4", acc, tile=512)
+    _check(got, oracle_mod.xcorr(packed, ns, npol, fmt=oracle_mod.CI4), f"super/{acc}/{shape}")
 
 
-def test_super_extreme_values(oracle_mod):
+@pytest.mark.parametrize("acc", ACCS)
+def test_super_extreme_values(oracle_mod, acc):
     """Full-scale 4-bit samples, some inputs pinned at -8 (the widened operand -64, whose
     rotation +64 still fits int8)."""
     ns, npol, F, T = 256, 2, 2, 150
@@ -50,9 +55,9 @@ def test_super_extreme_values(oracle_mod):
     v[:, :, :6] = -8
     v[:, :, 300:302] = 7
     packed = synth.pack_ci4(v)
-    say("super extreme")
-    got, _ = run_xeng(packed, ns, npol, "ci4", "i8", tile=512)
-    _check(got, oracle_mod.xcorr(packed, ns, npol, fmt=oracle_mod.CI4), "super-extreme")
+    say("super extreme", acc)
+    got, _ = run_xeng(packed, ns, npol, "ci4", acc, tile=512)
+    _check(got, oracle_mod.xcorr(packed, ns, npol, fmt=oracle_mod.CI4), f"super-extreme/{acc}")
 
 
 # channels sampled from a walk over 150 channels of 512 inputs (4 pieces each, 600 items):
@@ -60,24 +65,47 @@ def test_super_extreme_values(oracle_mod):
 WALK_CHANS = [0, 1, 31, 32, 63, 64, 65, 127, 128, 149]
 
 
-def test_super_many_items_per_workgroup(oracle_mod):
+@pytest.mark.parametrize("acc", ACCS)
+def test_super_many_items_per_workgroup(oracle_mod, acc):
     ns, npol, F, T = 256, 2, 150, 40
     v = synth.voltages_np(synth.SEED_BASE + 62, T, F, ns * npol, ("uniform", -8, 7))
     packed = synth.pack_ci4(v)
-    say("super walk", F)
-    got, _ = run_xeng(packed, ns, npol, "ci4", "i8", tile=512)
+    say("super walk", acc, F)
+    got, _ = run_xeng(packed, ns, npol, "ci4", acc, tile=512)
     want = oracle_mod.xcorr(packed, ns, npol, fmt=oracle_mod.CI4, chans=WALK_CHANS)
-    _check(got[WALK_CHANS], want, "super-walk")
+    _check(got[WALK_CHANS], want, f"super-walk/{acc}")
 
 
-def test_super_equals_tiles():
+@pytest.mark.parametrize("acc", ACCS)
+def test_super_equals_tiles(acc):
     """Super-tiles and 128-tiles give the same bits."""
     ns, npol, F, T = 512, 2, 3, 200
     v = synth.voltages_np(synth.SEED_BASE + 63, T, F, ns * npol, ("uniform", -8, 7))
     packed = synth.pack_ci4(v)
-    a, _ = run_xeng(packed, ns, npol, "ci4", "i8", tile=512)
-    b, _ = run_xeng(packed, ns, npol, "ci4", "i8", tile=128)
+    a, _ = run_xeng(packed, ns, npol, "ci4", acc, tile=512)
+    b, _ = run_xeng(packed, ns, npol, "ci4", acc, tile=128)
     assert np.array_equal(a, b)
+
+
+def test_super_f8_windows():
+    """fp8 super-tiles with two fp32 windows (131072 samples each at the default bound)
+    summed into fp64 totals: the totals equal, exactly, the sums of the two halves run as
+    single-window jobs (time split linearity; single windows are pinned to the oracle by
+    the tests above)."""
+    from paper_1107_4264_amd import xcorr as X
+
+    ns, npol, F, T1, T2 = 256, 2, 1, 131072, 300
+    p = X.xcorr_plan(ns, npol, F, T1 + T2, X.IN_CI4, X.ACC_F8E4M3_MMA_F32, 0)
+    assert p["tile"] == 512 and p["nwindows"] == 2 and p["out_dtype"] == X.OUT_C128
+    v = synth.voltages_np(synth.SEED_BASE + 66, T1 + T2, F, ns * npol, ("uniform", -8, 7))
+    packed = synth.pack_ci4(v)
+    say("super f8 windows", T1 + T2)
+    full, ot = run_xeng(packed, ns, npol, "ci4", "f8")
+    assert ot == X.OUT_C128
+    a, ota = run_xeng(packed[:T1], ns, npol, "ci4", "f8")
+    b, _ = run_xeng(packed[T1:], ns, npol, "ci4", "f8")
+    assert ota == X.OUT_C64
+    assert np.array_equal(as_exact_int(full), as_exact_int(a) + as_exact_int(b))
 
 
 def test_super_stream_accumulates(oracle_mod):
