@@ -17,7 +17,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libxcorr.so")
 OBJDIR = os.path.join(HERE, "_build")
 
-SOURCES = ["api.cpp", "plan.cpp", "tune.cpp", "xeng_mfma.hip", "xeng_chan.hip", "xeng_cmac.hip", "xeng_util.hip"]
+SOURCES = ["api.cpp", "plan.cpp", "tune.cpp", "xeng_mfma.hip", "xeng_chan.hip", "xeng_super.hip", "xeng_cmac.hip",
+           "xeng_util.hip"]
 
 ARCH = "gfx950"
 # Packed FP32 VALU instructions are switched off for all device code.

@@ -1,0 +1,353 @@
+// Super-tiled X-engine on the CDNA4 matrix cores (gfx950) for arrays of 256 S inputs
+// (S = 2..8) with 4-bit complex samples, on the int8 and fp8 paths.
+//
+// A channel's triangle (Eq. 4) is cut into S diagonal triangles of 256 inputs (the 36-block
+// work lists of the whole-channel kernel) and S (S - 1) rectangles of 256 row inputs x 128
+// column inputs (32 blocks, one 2x2 square per wave), run as two launches (one work list per
+// kernel).  An item is (window, channel, piece); consecutive items go to workgroups of one
+// XCD, so the pieces of a channel share their rows through its L2.  Per block of SP_TB time
+// rows, the piece's input segments (256 row inputs and, for a rectangle, 128 column inputs)
+// are copied into a raw LDS ring (one byte per sample), then widened once into the layout
+// the whole-channel kernel's int8 path reads (two bytes per sample, 16-byte chunks
+// XOR-swizzled by row):
+//   * int8: both components scaled by 8, exactly: 8 re = ((b & 0xF0) >> 1) | (b & 0x80) per
+//     byte, and the same after moving the low nibble up; the products carry a factor 64,
+//     divided out exactly before the stores (the planner keeps such jobs to one window of
+//     floor((2^31 - 1) / (128 m^2)) samples);
+//   * fp8: e4m3 pairs (all of -8..7 are exact), with the usual fp32 windows.
+// The K-steps (software pipelined, Sec. 4.4's staging re-planned for gfx950), rotations and
+// stores are those of the whole-channel kernel.
+
+#include "xeng_chan_dev.h"
+
+namespace xc {
+namespace {
+
+constexpr int SP_TB = 32, SP_RING = 5;
+constexpr int SP_AROW = 256, SP_BROW = 128;          // raw bytes per time row of the two segments
+constexpr int SP_RAW = SP_TB * (SP_AROW + SP_BROW);   // raw bytes per block
+constexpr int SP_CROW = 768;                          // widened bytes per time row (384 inputs)
+constexpr int SP_CONV = SP_TB * SP_CROW;              // widened bytes per block
+constexpr int SP_LDS = SP_RING * SP_RAW + 2 * SP_CONV;
+constexpr int SP_DPW = 2;                             // copies per wave per block
+
+// Rectangle pieces: wave W takes block rows {2 (W/2), 2 (W/2) + 1} and the column blocks
+// {2 (W%2), 2 (W%2) + 1} of the column segment, stored as fragment rows 8..11.
+template <int W>
+struct RectSpec : SquareSpec<(W >> 1), 4 + (W & 1)> {};
+
+// Position in the work of a workgroup: item g = step * grid + pos, pos = (b % 8) grid / 8 +
+// b / 8 when the grid is a multiple of 8 (consecutive items on one XCD); item
+// g = (window * nchan + channel) * npiece + piece.  All fields are wave-uniform.
+template <int TRI>
+struct SCursor {
+    int64_t step;
+    int pos, blk, nblk, f, t0, t1;
+    int seg_a, seg_b;  // first row input, first column input of the piece
+    bool valid;
+
+    __device__ __forceinline__ void set(const XJob &p, int64_t st)
+    {
+        step = st;
+        blk = 0;
+        const int64_t g = st * p.grid + pos;
+        valid = g < p.nitems;
+        if (valid) {
+            const int ns = p.ntile_side, np = TRI ? ns : ns * (ns - 1);
+            const int piece = (int)(g % np);
+            const int64_t q = g / np;
+            const int w = (int)(q / p.nchan);
+            f = (int)(q - (int64_t)w * p.nchan);
+            t0 = w * p.window;
+            t1 = min(p.ntime, t0 + p.window);
+            nblk = (t1 - t0 + SP_TB - 1) / SP_TB;
+            if (TRI) {
+                seg_a = seg_b = 256 * piece;
+            } else {
+                // piece = 2 (i (i - 1) / 2 + j) + h for super-rows j < i, half h
+                const int h = piece & 1;
+                int pr = piece >> 1, i = 1;
+                while (pr >= i) {
+                    pr -= i;
+                    ++i;
+                }
+                seg_a = 256 * i;
+                seg_b = 256 * pr + 128 * h;
+            }
+        } else {  // past the end: empty blocks
+            f = 0;
+            t0 = t1 = 0;
+            nblk = 1;
+            seg_a = seg_b = 0;
+        }
+    }
+    __device__ __forceinline__ void init(const XJob &p)
+    {
+        const int b = blockIdx.x, G = (int)p.grid;
+        pos = (G % 8 == 0) ? (b % 8) * (G / 8) + b / 8 : b;
+        set(p, 0);
+    }
+    __device__ __forceinline__ void next(const XJob &p)
+    {
+        if (++blk == nblk) set(p, step + 1);
+    }
+};
+
+// Descriptor of one input segment of the block the cursor points at (bytes `len` of each
+// row from input `first`); len 0 reads zeros.
+template <typename C>
+__device__ __forceinline__ i32x4s seg_rsrc(const XJob &p, const C &c, int first, int len, uint64_t row_stride)
+{
+    const int r0 = c.t0 + c.blk * SP_TB;
+    const int nrows = len ? max(0, min(SP_TB, c.t1 - r0)) : 0;
+    const uint64_t base = (uint64_t)p.in + ((uint64_t)r0 * p.nchan + c.f) * (uint64_t)p.nin + first;
+    const uint32_t nrec = nrows ? (uint32_t)((nrows - 1) * row_stride + len) : 0u;
+    i32x4s r;
+    r[0] = __builtin_amdgcn_readfirstlane((int)(uint32_t)base);
+    r[1] = __builtin_amdgcn_readfirstlane((int)((uint32_t)(base >> 32) & 0xFFFFu));
+    r[2] = __builtin_amdgcn_readfirstlane((int)nrec);
+    r[3] = 0x00020000;
+    return r;
+}
+
+// Four 4-bit complex samples (one per byte: re high nibble, im low) -> two words of
+// (8 re, 8 im) int8 pairs.
+// e4m3 codes of four signed 4-bit values (one per byte, low nibble): two 8-entry byte
+// tables (values 0..7 and -8..-1, indexed by the low three bits) and the sign bit of each
+// nibble spread to a byte mask ((t << 8) - t is 0xFF per byte where t is 1, no carries).
+__device__ __forceinline__ uint32_t nibbles_to_e4m3(uint32_t n)
+{
+    const uint32_t idx = n & 0x07070707u;
+    const uint32_t pos = __builtin_amdgcn_perm(0x4E4C4A48u, 0x44403800u, idx);  // 0, 1, .., 7
+    const uint32_t neg = __builtin_amdgcn_perm(0xB8C0C4C8u, 0xCACCCED0u, idx);  // -8, -7, .., -1
+    const uint32_t t = (n >> 3) & 0x01010101u;
+    const uint32_t m = (t << 8) - t;
+    return (neg & m) | (pos & ~m);
+}
+
+// Four 4-bit complex samples (one per byte: re high nibble, im low) -> two words of
+// (re, im) fp8 e4m3 pairs, exactly.
+__device__ __forceinline__ void ci4x4_to_e4m3x8(uint32_t w, uint32_t &lo, uint32_t &hi)
+{
+    const uint32_t re = nibbles_to_e4m3((w >> 4) & 0x0F0F0F0Fu);
+    const uint32_t im = nibbles_to_e4m3(w & 0x0F0F0F0Fu);
+    lo = __builtin_amdgcn_perm(im, re, 0x05010400u);
+    hi = __builtin_amdgcn_perm(im, re, 0x07030602u);
+}
+
+__device__ __forceinline__ void ci4x4_to_i8x8(uint32_t w, uint32_t &lo, uint32_t &hi)
+{
+    const uint32_t t = w & 0xF0F0F0F0u;
+    const uint32_t re = (t >> 1) | (t & 0x80808080u);
+    const uint32_t u = (w << 4) & 0xF0F0F0F0u;
+    const uint32_t im = (u >> 1) | (u & 0x80808080u);
+    lo = __builtin_amdgcn_perm(im, re, 0x05010400u);
+    hi = __builtin_amdgcn_perm(im, re, 0x07030602u);
+}
+
+// int8: the operands are 8 x the samples, the sums 64 x the visibilities (exact shift)
+template <int ACC, typename S>
+__device__ __forceinline__ void descale_store(const XJob &p, int f, int lane, AccSet<ACC> &acc, int row_base,
+                                              int col_base)
+{
+    if constexpr (ACC == ACC_I8) {
+#pragma unroll
+        for (int x = 0; x < S::NB; ++x) {
+            acc.re[x] = acc.re[x] >> 6;
+            acc.im[x] = acc.im[x] >> 6;
+        }
+    }
+    store_all<ACC, S>(p, f, lane, acc, row_base, col_base);
+}
+
+template <int ACC, int TRI, int W>
+__device__ __forceinline__ void run_wave_super(const XJob &p, int lane)
+{
+    constexpr int RING = SP_RING, DPW = SP_DPW, NKS = SP_TB / COp<ACC>::KS;
+    static_assert(NKS >= 1 && SP_TB % COp<ACC>::KS == 0, "whole K-steps per block");
+    using acc_t = typename COp<ACC>::acc_t;
+    using S = typename std::conditional<TRI != 0, Spec<W>, RectSpec<W>>::type;
+    constexpr int NU = TRI ? 2 : 3;    // widening instructions per wave per block
+    constexpr int NCH = TRI ? 32 : 48; // 16-byte chunks of a widened row
+    const uint64_t row_stride = (uint64_t)p.nchan * p.nin;
+    const uint32_t lds0 = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) uint8_t *)chan_lds;
+    const uint32_t conv0 = lds0 + RING * SP_RAW;
+
+    // copies: instruction A of wave W fills segment-A rows 4W .. 4W + 3 (16 chunks each),
+    // instruction B of waves W and W + 4 the segment-B rows 8 (W % 4) .. + 7 (8 chunks each;
+    // both waves write the same bytes)
+    const int wb = W & 3;
+    const uint32_t voff_a = (uint32_t)((4 * W + (lane >> 4)) * row_stride + 16 * (lane & 15));
+    const uint32_t voff_b = (uint32_t)((8 * wb + (lane >> 3)) * row_stride + 16 * (lane & 7));
+    auto issue = [&](const SCursor<TRI> &c, int slot, int m) __attribute__((always_inline)) {
+        const uint32_t sb = lds0 + slot * SP_RAW;
+        if (m == 0) dma16(seg_rsrc(p, c, c.seg_a, SP_AROW, row_stride), sb + 4 * W * SP_AROW, voff_a);
+        else dma16(seg_rsrc(p, c, c.seg_b, TRI ? 0 : SP_BROW, row_stride), sb + SP_TB * SP_AROW + 8 * wb * SP_BROW,
+                   voff_b);
+    };
+
+    // widening units: instruction m < NU of wave W covers unit U = 512 m + 64 W + lane, row
+    // U / NCH, chunk U % NCH (chunks 0..31 from segment A, 32..47 from segment B)
+    static_assert(NU * 512 == SP_TB * NCH, "units cover the block");
+    uint32_t usrc[NU], udst[NU];
+#pragma unroll
+    for (int m = 0; m < NU; ++m) {
+        const int U = 512 * m + 64 * W + lane;
+        const int row = U / NCH, c = U - NCH * (U / NCH);
+        usrc[m] = (uint32_t)(c < 32 ? row * SP_AROW + 8 * c : SP_TB * SP_AROW + row * SP_BROW + 8 * (c - 32));
+        udst[m] = (uint32_t)(row * SP_CROW + 16 * (c ^ (4 * (row & 3))));
+    }
+    typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+    typedef __attribute__((address_space(3))) u32x2 lds_u2;
+    auto widen = [&](u32x2 v, uint32_t dst) __attribute__((always_inline)) {
+        uint32_t o0, o1, o2, o3;
+        if constexpr (ACC == ACC_I8) {
+            ci4x4_to_i8x8(v[0], o0, o1);
+            ci4x4_to_i8x8(v[1], o2, o3);
+        } else {
+            ci4x4_to_e4m3x8(v[0], o0, o1);
+            ci4x4_to_e4m3x8(v[1], o2, o3);
+        }
+        *(lds_u4 *)(uintptr_t)dst = (u32x4){o0, o1, o2, o3};
+    };
+    auto raw_read = [&](uint32_t a) __attribute__((always_inline)) { return *(const lds_u2 *)(uintptr_t)a; };
+    // the whole widening of one block (prologue)
+    auto widen_block = [&](uint32_t src, uint32_t dst) __attribute__((always_inline)) {
+#pragma unroll
+        for (int m = 0; m < NU; ++m) widen(raw_read(src + usrc[m]), dst + udst[m]);
+    };
+
+    uint32_t lb[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) lb[q] = conv0 + lane_base<ACC, SP_CROW>(lane, q);
+
+    AccSet<ACC> acc;
+#pragma unroll
+    for (int x = 0; x < MAXB; ++x) {
+        acc.re[x] = (acc_t){};
+        acc.im[x] = (acc_t){};
+    }
+
+    SCursor<TRI> dc, nc, cc;
+    dc.init(p);
+    cc.init(p);
+    nc.init(p);
+#pragma unroll
+    for (int d = 0; d < RING - 1; ++d) {
+        issue(dc, d, 0);
+        issue(dc, d, 1);
+        dc.next(p);
+    }
+    nc.next(p);  // the block after cc's
+
+    wait_vm<(RING - 2) * DPW>();
+    __syncthreads();
+    widen_block(lds0, conv0);
+    int slot = 0, fb = 0, ready = 0;
+    while (cc.valid) {
+        // the copy of the next block (own, then everyone's) and the widening of this one
+        // are complete; the raw slot of the previous block and the other buffer are free
+        if (ready == 0) wait_vm<(RING - 3) * DPW>();
+        else --ready;
+        __syncthreads();
+        const SCursor<TRI> ic = dc;
+        const int dslot = slot == 0 ? RING - 1 : slot - 1;
+        dc.next(p);
+        const uint32_t csrc = lds0 + (slot == RING - 1 ? 0 : slot + 1) * SP_RAW;
+        const uint32_t cdst = conv0 + (fb ^ 1) * SP_CONV;
+        uint32_t lv[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) lv[q] = lb[q] + fb * SP_CONV;
+        // K-step k issues copy m (of the block RING - 1 ahead) when m NKS / DPW == k, and
+        // widens unit u of the next block when u NKS / NU == k: the unit is read before the
+        // MFMAs, widened and stored between them
+        u32x2 rr[NU];
+        auto copy = [&](auto K) __attribute__((always_inline)) {
+            static_for<DPW>([&](auto M) __attribute__((always_inline)) {
+                if constexpr (decltype(M)::value * NKS / DPW == decltype(K)::value) issue(ic, dslot, decltype(M)::value);
+            });
+        };
+        auto pre = [&](auto K) __attribute__((always_inline)) {
+            static_for<NU>([&](auto U) __attribute__((always_inline)) {
+                constexpr int u = decltype(U)::value;
+                if constexpr (u * NKS / NU == decltype(K)::value) rr[u] = raw_read(csrc + usrc[u]);
+            });
+        };
+        auto mid = [&](auto K) __attribute__((always_inline)) {
+            static_for<NU>([&](auto U) __attribute__((always_inline)) {
+                constexpr int u = decltype(U)::value;
+                if constexpr (u * NKS / NU == decltype(K)::value) widen(rr[u], cdst + udst[u]);
+            });
+        };
+        block_raw<ACC, S, NKS, SP_CROW>(lv, acc, copy, mid, pre);
+        slot = slot == RING - 1 ? 0 : slot + 1;
+        fb ^= 1;
+        nc.next(p);
+
+        if (++cc.blk == cc.nblk) {
+            wait_vm<0>();
+            ready = RING - 2;
+            descale_store<ACC, S>(p, cc.f, lane, acc, cc.seg_a, cc.seg_b);
+#pragma unroll
+            for (int x = 0; x < MAXB; ++x) {
+                acc.re[x] = (acc_t){};
+                acc.im[x] = (acc_t){};
+            }
+            cc.set(p, cc.step + 1);
+        }
+    }
+    // no copy into LDS may outlive the workgroup
+    wait_vm<0>();
+}
+
+template <int ACC, int TRI>
+__global__ __launch_bounds__(CT, 1) void xeng_super_kernel(XJob p)
+{
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    switch (wave) {
+    case 0: run_wave_super<ACC, TRI, 0>(p, lane); break;
+    case 1: run_wave_super<ACC, TRI, 1>(p, lane); break;
+    case 2: run_wave_super<ACC, TRI, 2>(p, lane); break;
+    case 3: run_wave_super<ACC, TRI, 3>(p, lane); break;
+    case 4: run_wave_super<ACC, TRI, 4>(p, lane); break;
+    case 5: run_wave_super<ACC, TRI, 5>(p, lane); break;
+    case 6: run_wave_super<ACC, TRI, 6>(p, lane); break;
+    default: run_wave_super<ACC, TRI, 7>(p, lane); break;
+    }
+}
+
+template <int ACC, int TRI>
+int launch_super_kind(XJob job, int cus, hipStream_t stream)
+{
+    static int done = 0;
+    if (!done) {
+        const hipError_t e = hipFuncSetAttribute((const void *)xeng_super_kernel<ACC, TRI>,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, SP_LDS);
+        if (e != hipSuccess) return (int)e;
+        done = 1;
+    }
+    const int ns = job.ntile_side;
+    job.nitems = (int64_t)job.nwindows * job.nchan * (TRI ? ns : ns * (ns - 1));
+    job.grid = job.nitems < cus ? job.nitems : cus;
+    if (job.grid <= 0) return 0;
+    hipLaunchKernelGGL((xeng_super_kernel<ACC, TRI>), dim3((unsigned)job.grid), dim3(CT), SP_LDS, stream, job);
+    return (int)hipGetLastError();
+}
+
+}  // namespace
+
+int launch_super(const XJob &job, int acc, int cus, hipStream_t stream)
+{
+    if (acc == ACC_I8) {
+        if (int e = launch_super_kind<ACC_I8, 1>(job, cus, stream)) return e;
+        return launch_super_kind<ACC_I8, 0>(job, cus, stream);
+    }
+    if (acc == ACC_F8) {
+        if (int e = launch_super_kind<ACC_F8, 1>(job, cus, stream)) return e;
+        return launch_super_kind<ACC_F8, 0>(job, cus, stream);
+    }
+    return (int)hipErrorInvalidValue;
+}
+
+}  // namespace xc
