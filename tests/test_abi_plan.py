@@ -251,3 +251,12 @@ def test_super_tile_rejected(args):
     ns, npol, F, T, fmt, acc = args
     with pytest.raises(X.XcorrError):
         X.xcorr_plan(ns, npol, F, T, getattr(X, fmt), getattr(X, acc), 0, 512)
+
+
+def test_super_tile_f8_windows():
+    # fp8 super-tiles keep the usual fp32 windows (2^24 / (2 m^2) samples, m = 8 for 4-bit)
+    p = X.xcorr_plan(256, 2, 1, 131072, X.IN_CI4, X.ACC_F8E4M3_MMA_F32, 0)
+    assert p["tile"] == 512 and p["nwindows"] == 1 and p["out_dtype"] == X.OUT_C64
+    p = X.xcorr_plan(256, 2, 1, 131072 + 300, X.IN_CI4, X.ACC_F8E4M3_MMA_F32, 0)
+    assert p["tile"] == 512 and p["nwindows"] == 2 and p["out_dtype"] == X.OUT_C128
+    assert p["window"] == 131072
