@@ -126,9 +126,10 @@ int xcorr_set_max_abs(xcorr_handle_t *h, int max_abs);
  *        128-tiles instead;
  *   512  super-tiles: the triangle of each channel cut into 256-input triangles and
  *        256 x 128 rectangles, each held by one persistent workgroup (two launches); needs
- *        CI4 input, the int8 or fp8 path and nin a multiple of 256 in 512..2048; on the
- *        int8 path also ntime <= (2^31 - 1) / (128 max_abs^2) (its operands are the
- *        samples times 8).  Same alignment fallback.
+ *        CI4 input on the int8 or fp8 path, or CI8 input on the int8 path, and nin a
+ *        multiple of 256 in 512..2048; for CI4 on the int8 path also
+ *        ntime <= (2^31 - 1) / (128 max_abs^2) (its operands are the samples times 8).
+ *        Same alignment fallback.
  * All shapes give bit-identical visibilities.  XCORR_ERR_INVALID_ARG for a shape the job
  * does not allow (the handle keeps its previous shape). */
 int xcorr_set_tile(xcorr_handle_t *h, int tile);

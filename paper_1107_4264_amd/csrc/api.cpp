@@ -82,7 +82,7 @@ int launch_job(const Plan &pl, XJob j, hipStream_t stream)
         if ((uintptr_t)j.in % 16 == 0) {
             const int cus = device_cus();
             if (cus <= 0) return (int)hipErrorNoDevice;
-            if (pl.tile == SUPER_TILE) return launch_super(j, pl.acc, cus, stream);
+            if (pl.tile == SUPER_TILE) return launch_super(j, pl.acc, pl.in_fmt, cus, stream);
             j.grid = std::min<int64_t>(pl.nitems, cus);
             return launch_chan(j, pl.acc, stream);
         }

@@ -77,13 +77,14 @@ bool chan_kernel_ok(int nin, int in_fmt, int acc)
 
 bool super_kernel_ok(int nin, int nchan, int64_t ntime, int in_fmt, int acc, int max_abs)
 {
-    if (in_fmt != IN_CI4 || (acc != ACC_I8 && acc != ACC_F8) || nin % 256 != 0 || nin < 512 || nin > 2048)
-        return false;
+    const bool fmt_ok = (in_fmt == IN_CI4 && (acc == ACC_I8 || acc == ACC_F8)) || (in_fmt == IN_CI8 && acc == ACC_I8);
+    if (!fmt_ok || nin % 256 != 0 || nin < 512 || nin > 2048) return false;
     // the copy offsets of a block (32 rows) stay below 2^32 bytes
-    if (32 * (int64_t)nchan * nin >= ((int64_t)1 << 32)) return false;
-    // fp8 operands are the samples themselves (the usual fp32 windows); int8 operands are
-    // 8 x the samples, so the whole job must fit one int32 window of the scaled sums
-    if (acc == ACC_F8) return true;
+    if (32 * (int64_t)nchan * nin * (int64_t)in_sample_bytes(in_fmt) >= ((int64_t)1 << 32)) return false;
+    // fp8 operands and int8 operands from 8-bit samples are the samples themselves (the
+    // usual windows); int8 operands from 4-bit samples are 8 x the samples, so the whole job
+    // must fit one int32 window of the scaled sums
+    if (acc == ACC_F8 || in_fmt == IN_CI8) return true;
     const int64_t m = max_abs;
     return m >= 1 && ntime <= (int64_t)2147483647 / (128 * m * m);
 }
@@ -160,8 +161,9 @@ int make_plan(int nstation, int npol, int nchan, int ntime, int in_fmt, int acc,
     // Above 192 inputs the whole-channel kernel computes at most 36/28 of the useful blocks
     // and reads every sample once, in whole rows.
     if (chan_kernel_ok(p.nin, in_fmt, acc) && p.nin > 192) tile = CHAN_TILE;
-    // From 512 inputs of 4-bit samples on the int8 path, super-tiles: whole 256-input
-    // pieces per workgroup, operands widened once per block in LDS.
+    // From 512 inputs (a multiple of 256) of 4-bit samples on the int8 / fp8 paths and of
+    // 8-bit samples on the int8 path, super-tiles: whole 256-input pieces per workgroup,
+    // operands widened (or moved) once per block in LDS.
     if (super_kernel_ok(p.nin, nchan, ntime, in_fmt, acc, max_abs)) tile = SUPER_TILE;
     if (tile_override) {
         bool ok;

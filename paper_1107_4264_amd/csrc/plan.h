@@ -39,9 +39,10 @@ bool chan_kernel_ok(int nin, int in_fmt, int acc);
 // arrays of 512..2048 inputs, 4-bit samples, int8 and fp8 paths.
 constexpr int SUPER_TILE = 512;
 
-// Whether the super-tiled kernel accepts a job: CI4 samples on the int8 or fp8 path, nin a
-// multiple of 256 in 512..2048; on the int8 path also one window of its scaled operands
-// (floor((2^31-1)/(128 m^2)) samples for samples bounded by m).
+// Whether the super-tiled kernel accepts a job: CI4 samples on the int8 or fp8 path or CI8
+// samples on the int8 path, nin a multiple of 256 in 512..2048; for CI4 on the int8 path
+// also one window of its scaled operands (floor((2^31-1)/(128 m^2)) samples for samples
+// bounded by m).
 bool super_kernel_ok(int nin, int nchan, int64_t ntime, int in_fmt, int acc, int max_abs);
 
 // Exact inverse of g = by*(by+1)/2 + bx, 0 <= bx <= by.

@@ -49,7 +49,7 @@ int launch_zero(void *ptr, size_t bytes, hipStream_t stream);
 // Whole-channel kernel (tile 256): persistent, job.grid workgroups of 512 threads walk the
 // job.nitems (channel, window) items, window-major.
 int launch_chan(const XJob &job, int acc, hipStream_t stream);
-int launch_super(const XJob &job, int acc, int cus, hipStream_t stream);
+int launch_super(const XJob &job, int acc, int in_fmt, int cus, hipStream_t stream);
 
 // Batched persistent launch.  The work list is split into NQUEUE queues (one per XCD: a
 // channel's items all go to one queue); workgroup b takes items from queue b % NQUEUE

@@ -1,5 +1,6 @@
 // Super-tiled X-engine on the CDNA4 matrix cores (gfx950) for arrays of 256 S inputs
-// (S = 2..8) with 4-bit complex samples, on the int8 and fp8 paths.
+// (S = 2..8): 4-bit complex samples on the int8 and fp8 paths, 8-bit samples on the int8
+// path.
 //
 // A channel's triangle (Eq. 4) is cut into S diagonal triangles of 256 inputs (the 36-block
 // work lists of the whole-channel kernel) and S (S - 1) rectangles of 256 row inputs x 128
@@ -7,9 +8,9 @@
 // kernel).  An item is (window, channel, piece); consecutive items go to workgroups of one
 // XCD, so the pieces of a channel share their rows through its L2.  Per block of SP_TB time
 // rows, the piece's input segments (256 row inputs and, for a rectangle, 128 column inputs)
-// are copied into a raw LDS ring (one byte per sample), then widened once into the layout
-// the whole-channel kernel's int8 path reads (two bytes per sample, 16-byte chunks
-// XOR-swizzled by row):
+// are copied into a raw LDS ring (one or two bytes per sample), then widened once into the
+// layout the whole-channel kernel's int8 path reads (two bytes per sample, 16-byte chunks
+// XOR-swizzled by row; 8-bit samples are only moved into that layout):
 //   * int8: both components scaled by 8, exactly: 8 re = ((b & 0xF0) >> 1) | (b & 0x80) per
 //     byte, and the same after moving the low nibble up; the products carry a factor 64,
 //     divided out exactly before the stores (the planner keeps such jobs to one window of
@@ -23,13 +24,26 @@
 namespace xc {
 namespace {
 
-constexpr int SP_TB = 32, SP_RING = 5;
-constexpr int SP_AROW = 256, SP_BROW = 128;          // raw bytes per time row of the two segments
-constexpr int SP_RAW = SP_TB * (SP_AROW + SP_BROW);   // raw bytes per block
-constexpr int SP_CROW = 768;                          // widened bytes per time row (384 inputs)
-constexpr int SP_CONV = SP_TB * SP_CROW;              // widened bytes per block
-constexpr int SP_LDS = SP_RING * SP_RAW + 2 * SP_CONV;
-constexpr int SP_DPW = 2;                             // copies per wave per block
+constexpr int SP_TB = 32;                  // time rows per block
+constexpr int SP_CROW = 768;               // widened bytes per time row (384 inputs)
+constexpr int SP_CONV = SP_TB * SP_CROW;   // widened bytes per block
+
+// Raw geometry per sample format: BPS bytes per sample; AROW / BROW raw bytes per time row
+// of the row / column segment; NA / NB copy instructions (1 KiB each) per block for them;
+// DPW copies per wave per block (NA / 8 row copies and one column copy, the column copies
+// repeated by two waves when NB = 4); UB raw bytes of one 16-byte widened chunk.
+template <int IN>
+struct SGeo {
+    static constexpr int BPS = IN == IN_CI8 ? 2 : 1;
+    static constexpr int AROW = 256 * BPS, BROW = 128 * BPS;
+    static constexpr int RAW = SP_TB * (AROW + BROW);
+    static constexpr int RING = IN == IN_CI8 ? 4 : 5;
+    static constexpr int LDS = RING * RAW + 2 * SP_CONV;
+    static constexpr int NA = SP_TB * AROW / 1024, NB = SP_TB * BROW / 1024;
+    static constexpr int DPW = NA / 8 + 1;
+    static constexpr int UB = 8 * BPS;
+    static_assert(NA % 8 == 0 && 8 % NB == 0 && LDS <= 160 * 1024, "copy split and LDS budget");
+};
 
 // Rectangle pieces: wave W takes block rows {2 (W/2), 2 (W/2) + 1} and the column blocks
 // {2 (W%2), 2 (W%2) + 1} of the column segment, stored as fragment rows 8..11.
@@ -94,13 +108,14 @@ struct SCursor {
 };
 
 // Descriptor of one input segment of the block the cursor points at (bytes `len` of each
-// row from input `first`); len 0 reads zeros.
+// row from input `first`, bps bytes per sample); len 0 reads zeros.
 template <typename C>
-__device__ __forceinline__ i32x4s seg_rsrc(const XJob &p, const C &c, int first, int len, uint64_t row_stride)
+__device__ __forceinline__ i32x4s seg_rsrc(const XJob &p, const C &c, int first, int len, uint64_t row_stride,
+                                           int bps)
 {
     const int r0 = c.t0 + c.blk * SP_TB;
     const int nrows = len ? max(0, min(SP_TB, c.t1 - r0)) : 0;
-    const uint64_t base = (uint64_t)p.in + ((uint64_t)r0 * p.nchan + c.f) * (uint64_t)p.nin + first;
+    const uint64_t base = (uint64_t)p.in + (((uint64_t)r0 * p.nchan + c.f) * (uint64_t)p.nin + first) * bps;
     const uint32_t nrec = nrows ? (uint32_t)((nrows - 1) * row_stride + len) : 0u;
     i32x4s r;
     r[0] = __builtin_amdgcn_readfirstlane((int)(uint32_t)base);
@@ -145,12 +160,13 @@ __device__ __forceinline__ void ci4x4_to_i8x8(uint32_t w, uint32_t &lo, uint32_t
     hi = __builtin_amdgcn_perm(im, re, 0x07030602u);
 }
 
-// int8: the operands are 8 x the samples, the sums 64 x the visibilities (exact shift)
-template <int ACC, typename S>
+// int8 from 4-bit samples: the operands are 8 x the samples, the sums 64 x the
+// visibilities (exact shift)
+template <int ACC, int IN, typename S>
 __device__ __forceinline__ void descale_store(const XJob &p, int f, int lane, AccSet<ACC> &acc, int row_base,
                                               int col_base)
 {
-    if constexpr (ACC == ACC_I8) {
+    if constexpr (ACC == ACC_I8 && IN == IN_CI4) {
 #pragma unroll
         for (int x = 0; x < S::NB; ++x) {
             acc.re[x] = acc.re[x] >> 6;
@@ -160,30 +176,38 @@ __device__ __forceinline__ void descale_store(const XJob &p, int f, int lane, Ac
     store_all<ACC, S>(p, f, lane, acc, row_base, col_base);
 }
 
-template <int ACC, int TRI, int W>
+template <int ACC, int IN, int TRI, int W>
 __device__ __forceinline__ void run_wave_super(const XJob &p, int lane)
 {
-    constexpr int RING = SP_RING, DPW = SP_DPW, NKS = SP_TB / COp<ACC>::KS;
+    using Gs = SGeo<IN>;
+    constexpr int RING = Gs::RING, DPW = Gs::DPW, NKS = SP_TB / COp<ACC>::KS;
+    constexpr int NAW = Gs::NA / 8;    // row-segment copies per wave per block
     static_assert(NKS >= 1 && SP_TB % COp<ACC>::KS == 0, "whole K-steps per block");
     using acc_t = typename COp<ACC>::acc_t;
     using S = typename std::conditional<TRI != 0, Spec<W>, RectSpec<W>>::type;
     constexpr int NU = TRI ? 2 : 3;    // widening instructions per wave per block
     constexpr int NCH = TRI ? 32 : 48; // 16-byte chunks of a widened row
-    const uint64_t row_stride = (uint64_t)p.nchan * p.nin;
+    const uint64_t row_stride = (uint64_t)p.nchan * p.nin * Gs::BPS;
     const uint32_t lds0 = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) uint8_t *)chan_lds;
-    const uint32_t conv0 = lds0 + RING * SP_RAW;
+    const uint32_t conv0 = lds0 + RING * Gs::RAW;
 
-    // copies: instruction A of wave W fills segment-A rows 4W .. 4W + 3 (16 chunks each),
-    // instruction B of waves W and W + 4 the segment-B rows 8 (W % 4) .. + 7 (8 chunks each;
-    // both waves write the same bytes)
-    const int wb = W & 3;
-    const uint32_t voff_a = (uint32_t)((4 * W + (lane >> 4)) * row_stride + 16 * (lane & 15));
-    const uint32_t voff_b = (uint32_t)((8 * wb + (lane >> 3)) * row_stride + 16 * (lane & 7));
+    // copies (1 KiB each, lane l to LDS byte 16 l): row-segment instruction ia = 8 m + W
+    // fills rows ia RA .. + RA - 1 (RA = 1024 / AROW), column-segment instruction W % NB the
+    // rows (W % NB) RB .. + RB - 1 (waves W and W + 4 write the same bytes when NB = 4)
+    constexpr int LA = Gs::AROW / 16, LB = Gs::BROW / 16;  // lanes per row
+    const int ib = W % Gs::NB;
+    uint32_t voff_a[NAW];
+#pragma unroll
+    for (int m = 0; m < NAW; ++m)
+        voff_a[m] = (uint32_t)(((8 * m + W) * (1024 / Gs::AROW) + lane / LA) * row_stride + 16 * (lane % LA));
+    const uint32_t voff_b = (uint32_t)((ib * (1024 / Gs::BROW) + lane / LB) * row_stride + 16 * (lane % LB));
     auto issue = [&](const SCursor<TRI> &c, int slot, int m) __attribute__((always_inline)) {
-        const uint32_t sb = lds0 + slot * SP_RAW;
-        if (m == 0) dma16(seg_rsrc(p, c, c.seg_a, SP_AROW, row_stride), sb + 4 * W * SP_AROW, voff_a);
-        else dma16(seg_rsrc(p, c, c.seg_b, TRI ? 0 : SP_BROW, row_stride), sb + SP_TB * SP_AROW + 8 * wb * SP_BROW,
-                   voff_b);
+        const uint32_t sb = lds0 + slot * Gs::RAW;
+        if (m < NAW)
+            dma16(seg_rsrc(p, c, c.seg_a, Gs::AROW, row_stride, Gs::BPS), sb + (8 * m + W) * 1024, voff_a[m]);
+        else
+            dma16(seg_rsrc(p, c, c.seg_b, TRI ? 0 : Gs::BROW, row_stride, Gs::BPS), sb + SP_TB * Gs::AROW + ib * 1024,
+                  voff_b);
     };
 
     // widening units: instruction m < NU of wave W covers unit U = 512 m + 64 W + lane, row
@@ -194,23 +218,34 @@ __device__ __forceinline__ void run_wave_super(const XJob &p, int lane)
     for (int m = 0; m < NU; ++m) {
         const int U = 512 * m + 64 * W + lane;
         const int row = U / NCH, c = U - NCH * (U / NCH);
-        usrc[m] = (uint32_t)(c < 32 ? row * SP_AROW + 8 * c : SP_TB * SP_AROW + row * SP_BROW + 8 * (c - 32));
+        usrc[m] = (uint32_t)(c < 32 ? row * Gs::AROW + Gs::UB * c
+                                    : SP_TB * Gs::AROW + row * Gs::BROW + Gs::UB * (c - 32));
         udst[m] = (uint32_t)(row * SP_CROW + 16 * (c ^ (4 * (row & 3))));
     }
     typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
     typedef __attribute__((address_space(3))) u32x2 lds_u2;
-    auto widen = [&](u32x2 v, uint32_t dst) __attribute__((always_inline)) {
-        uint32_t o0, o1, o2, o3;
-        if constexpr (ACC == ACC_I8) {
-            ci4x4_to_i8x8(v[0], o0, o1);
-            ci4x4_to_i8x8(v[1], o2, o3);
+    // raw unit: 8 bytes of 4-bit samples, or 16 bytes of 8-bit samples (already int8 pairs)
+    using raw_t = typename std::conditional<IN == IN_CI8, u32x4, u32x2>::type;
+    auto widen = [&](raw_t v, uint32_t dst) __attribute__((always_inline)) {
+        if constexpr (IN == IN_CI8) {
+            static_assert(ACC == ACC_I8, "8-bit samples: int8 path only");
+            *(lds_u4 *)(uintptr_t)dst = v;
         } else {
-            ci4x4_to_e4m3x8(v[0], o0, o1);
-            ci4x4_to_e4m3x8(v[1], o2, o3);
+            uint32_t o0, o1, o2, o3;
+            if constexpr (ACC == ACC_I8) {
+                ci4x4_to_i8x8(v[0], o0, o1);
+                ci4x4_to_i8x8(v[1], o2, o3);
+            } else {
+                ci4x4_to_e4m3x8(v[0], o0, o1);
+                ci4x4_to_e4m3x8(v[1], o2, o3);
+            }
+            *(lds_u4 *)(uintptr_t)dst = (u32x4){o0, o1, o2, o3};
         }
-        *(lds_u4 *)(uintptr_t)dst = (u32x4){o0, o1, o2, o3};
     };
-    auto raw_read = [&](uint32_t a) __attribute__((always_inline)) { return *(const lds_u2 *)(uintptr_t)a; };
+    auto raw_read = [&](uint32_t a) __attribute__((always_inline)) {
+        if constexpr (IN == IN_CI8) return (raw_t)(*(const lds_u4 *)(uintptr_t)a);
+        else return (raw_t)(*(const lds_u2 *)(uintptr_t)a);
+    };
     // the whole widening of one block (prologue)
     auto widen_block = [&](uint32_t src, uint32_t dst) __attribute__((always_inline)) {
 #pragma unroll
@@ -234,8 +269,8 @@ __device__ __forceinline__ void run_wave_super(const XJob &p, int lane)
     nc.init(p);
 #pragma unroll
     for (int d = 0; d < RING - 1; ++d) {
-        issue(dc, d, 0);
-        issue(dc, d, 1);
+#pragma unroll
+        for (int m = 0; m < DPW; ++m) issue(dc, d, m);
         dc.next(p);
     }
     nc.next(p);  // the block after cc's
@@ -253,7 +288,7 @@ __device__ __forceinline__ void run_wave_super(const XJob &p, int lane)
         const SCursor<TRI> ic = dc;
         const int dslot = slot == 0 ? RING - 1 : slot - 1;
         dc.next(p);
-        const uint32_t csrc = lds0 + (slot == RING - 1 ? 0 : slot + 1) * SP_RAW;
+        const uint32_t csrc = lds0 + (slot == RING - 1 ? 0 : slot + 1) * Gs::RAW;
         const uint32_t cdst = conv0 + (fb ^ 1) * SP_CONV;
         uint32_t lv[4];
 #pragma unroll
@@ -261,7 +296,7 @@ __device__ __forceinline__ void run_wave_super(const XJob &p, int lane)
         // K-step k issues copy m (of the block RING - 1 ahead) when m NKS / DPW == k, and
         // widens unit u of the next block when u NKS / NU == k: the unit is read before the
         // MFMAs, widened and stored between them
-        u32x2 rr[NU];
+        raw_t rr[NU];
         auto copy = [&](auto K) __attribute__((always_inline)) {
             static_for<DPW>([&](auto M) __attribute__((always_inline)) {
                 if constexpr (decltype(M)::value * NKS / DPW == decltype(K)::value) issue(ic, dslot, decltype(M)::value);
@@ -287,7 +322,7 @@ __device__ __forceinline__ void run_wave_super(const XJob &p, int lane)
         if (++cc.blk == cc.nblk) {
             wait_vm<0>();
             ready = RING - 2;
-            descale_store<ACC, S>(p, cc.f, lane, acc, cc.seg_a, cc.seg_b);
+            descale_store<ACC, IN, S>(p, cc.f, lane, acc, cc.seg_a, cc.seg_b);
 #pragma unroll
             for (int x = 0; x < MAXB; ++x) {
                 acc.re[x] = (acc_t){};
@@ -300,30 +335,31 @@ __device__ __forceinline__ void run_wave_super(const XJob &p, int lane)
     wait_vm<0>();
 }
 
-template <int ACC, int TRI>
+template <int ACC, int IN, int TRI>
 __global__ __launch_bounds__(CT, 1) void xeng_super_kernel(XJob p)
 {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     switch (wave) {
-    case 0: run_wave_super<ACC, TRI, 0>(p, lane); break;
-    case 1: run_wave_super<ACC, TRI, 1>(p, lane); break;
-    case 2: run_wave_super<ACC, TRI, 2>(p, lane); break;
-    case 3: run_wave_super<ACC, TRI, 3>(p, lane); break;
-    case 4: run_wave_super<ACC, TRI, 4>(p, lane); break;
-    case 5: run_wave_super<ACC, TRI, 5>(p, lane); break;
-    case 6: run_wave_super<ACC, TRI, 6>(p, lane); break;
-    default: run_wave_super<ACC, TRI, 7>(p, lane); break;
+    case 0: run_wave_super<ACC, IN, TRI, 0>(p, lane); break;
+    case 1: run_wave_super<ACC, IN, TRI, 1>(p, lane); break;
+    case 2: run_wave_super<ACC, IN, TRI, 2>(p, lane); break;
+    case 3: run_wave_super<ACC, IN, TRI, 3>(p, lane); break;
+    case 4: run_wave_super<ACC, IN, TRI, 4>(p, lane); break;
+    case 5: run_wave_super<ACC, IN, TRI, 5>(p, lane); break;
+    case 6: run_wave_super<ACC, IN, TRI, 6>(p, lane); break;
+    default: run_wave_super<ACC, IN, TRI, 7>(p, lane); break;
     }
 }
 
-template <int ACC, int TRI>
+template <int ACC, int IN, int TRI>
 int launch_super_kind(XJob job, int cus, hipStream_t stream)
 {
+    constexpr int LDS = SGeo<IN>::LDS;
     static int done = 0;
     if (!done) {
-        const hipError_t e = hipFuncSetAttribute((const void *)xeng_super_kernel<ACC, TRI>,
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize, SP_LDS);
+        const hipError_t e = hipFuncSetAttribute((const void *)xeng_super_kernel<ACC, IN, TRI>,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, LDS);
         if (e != hipSuccess) return (int)e;
         done = 1;
     }
@@ -331,22 +367,26 @@ int launch_super_kind(XJob job, int cus, hipStream_t stream)
     job.nitems = (int64_t)job.nwindows * job.nchan * (TRI ? ns : ns * (ns - 1));
     job.grid = job.nitems < cus ? job.nitems : cus;
     if (job.grid <= 0) return 0;
-    hipLaunchKernelGGL((xeng_super_kernel<ACC, TRI>), dim3((unsigned)job.grid), dim3(CT), SP_LDS, stream, job);
+    hipLaunchKernelGGL((xeng_super_kernel<ACC, IN, TRI>), dim3((unsigned)job.grid), dim3(CT), LDS, stream, job);
     return (int)hipGetLastError();
+}
+
+template <int ACC, int IN>
+int launch_super_pair(const XJob &job, int cus, hipStream_t stream)
+{
+    if (int e = launch_super_kind<ACC, IN, 1>(job, cus, stream)) return e;
+    return launch_super_kind<ACC, IN, 0>(job, cus, stream);
 }
 
 }  // namespace
 
-int launch_super(const XJob &job, int acc, int cus, hipStream_t stream)
+// Both launches of a super-tiled job (triangles, then rectangles); each sets its own item
+// count and grid (at most one workgroup per compute unit, `cus`).
+int launch_super(const XJob &job, int acc, int in_fmt, int cus, hipStream_t stream)
 {
-    if (acc == ACC_I8) {
-        if (int e = launch_super_kind<ACC_I8, 1>(job, cus, stream)) return e;
-        return launch_super_kind<ACC_I8, 0>(job, cus, stream);
-    }
-    if (acc == ACC_F8) {
-        if (int e = launch_super_kind<ACC_F8, 1>(job, cus, stream)) return e;
-        return launch_super_kind<ACC_F8, 0>(job, cus, stream);
-    }
+    if (in_fmt == IN_CI4 && acc == ACC_I8) return launch_super_pair<ACC_I8, IN_CI4>(job, cus, stream);
+    if (in_fmt == IN_CI4 && acc == ACC_F8) return launch_super_pair<ACC_F8, IN_CI4>(job, cus, stream);
+    if (in_fmt == IN_CI8 && acc == ACC_I8) return launch_super_pair<ACC_I8, IN_CI8>(job, cus, stream);
     return (int)hipErrorInvalidValue;
 }
 

@@ -194,6 +194,10 @@ def test_tile_choice(acc):
     assert tile(512, 2, fmt=X.IN_CI4) == (512 if acc == X.ACC_I8_MMA_I32 else 128)
     assert tile(512, 2, fmt=X.IN_CI4, a=X.ACC_F8E4M3_MMA_F32) == 512
     assert tile(260, 2, fmt=X.IN_CI4) == 128
+    # 8-bit samples from 512 inputs: super-tiles on the int8 path only
+    assert tile(256, 2) == (512 if acc == X.ACC_I8_MMA_I32 else 128)
+    assert tile(384, 2) == (512 if acc == X.ACC_I8_MMA_I32 else 128)
+    assert tile(250, 2) == 128
     # explicit shapes
     assert tile(32, 2, 256) == 256    # allowed below the automatic threshold
     assert tile(128, 2, 128) == 128
@@ -244,7 +248,7 @@ def test_super_tile_plan():
     (128, 2, 4, 100, "IN_CI4", "ACC_I8_MMA_I32"),   # 256 inputs: below 512
     (200, 2, 4, 100, "IN_CI4", "ACC_I8_MMA_I32"),   # 400 inputs: not a multiple of 256
     (1280, 2, 4, 100, "IN_CI4", "ACC_I8_MMA_I32"),  # 2560 inputs: above 2048
-    (256, 2, 4, 100, "IN_CI8", "ACC_I8_MMA_I32"),   # 8-bit samples
+    (256, 2, 4, 100, "IN_CI8", "ACC_F16_MMA_F32"),  # 8-bit samples on the fp16 path
     (256, 2, 4, 100, "IN_CI4", "ACC_F16_MMA_F32"),  # fp16 path
 ])
 def test_super_tile_rejected(args):
@@ -260,3 +264,13 @@ def test_super_tile_f8_windows():
     p = X.xcorr_plan(256, 2, 1, 131072 + 300, X.IN_CI4, X.ACC_F8E4M3_MMA_F32, 0)
     assert p["tile"] == 512 and p["nwindows"] == 2 and p["out_dtype"] == X.OUT_C128
     assert p["window"] == 131072
+
+
+def test_super_tile_ci8():
+    # 8-bit samples on the int8 path: super-tiles on request, usual windows
+    p = X.xcorr_plan(512, 2, 4, 100, X.IN_CI8, X.ACC_I8_MMA_I32, 0, 512)
+    assert p["tile"] == 512 and p["tiles_per_chan"] == 16 and p["out_dtype"] == X.OUT_CI32
+    p = X.xcorr_plan(256, 2, 1, 66572 + 200, X.IN_CI8, X.ACC_I8_MMA_I32, 0, 512)
+    assert p["nwindows"] == 2 and p["out_dtype"] == X.OUT_CI64
+    with pytest.raises(X.XcorrError):
+        X.xcorr_plan(256, 2, 4, 100, X.IN_CI8, X.ACC_F16_MMA_F32, 0, 512)

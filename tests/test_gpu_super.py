@@ -153,3 +153,45 @@ def test_super_misaligned_input_falls_back(oracle_mod):
     torch.cuda.synchronize()
     _check(out.cpu().numpy(), oracle_mod.xcorr(packed, ns, npol, fmt=oracle_mod.CI4), "super-misaligned")
     c.close()
+
+
+CI8_SHAPES = [(256, 2, 3, 100), (384, 2, 2, 77), (512, 1, 2, 33), (256, 2, 1, 1)]
+
+
+@pytest.mark.parametrize("shape", CI8_SHAPES, ids=lambda s: "x".join(map(str, s)))
+def test_super_ci8_matches_oracle(oracle_mod, shape):
+    """8-bit samples on super-tiles (int8 path): rows moved into the operand layout."""
+    ns, npol, F, T = shape
+    x = synth.voltages_np(synth.SEED_BASE + 70 + ns + T, T, F, ns * npol, ("gauss", 40.0, 127))
+    say("super ci8", shape)
+    got, _ = run_xeng(x, ns, npol, "ci8", "i8", tile=512)
+    _check(got, oracle_mod.xcorr(x, ns, npol), f"super-ci8/{shape}")
+
+
+def test_super_ci8_extreme_and_tiles(oracle_mod):
+    """Full-scale 8-bit samples (+-127) on super-tiles equal the oracle and the 128-tiles."""
+    ns, npol, F, T = 256, 2, 2, 90
+    x = synth.voltages_np(synth.SEED_BASE + 71, T, F, ns * npol, ("uniform", -127, 127))
+    x[:, :, :4] = -127
+    x[:, :, 500:502] = 127
+    a, _ = run_xeng(x, ns, npol, "ci8", "i8", tile=512)
+    _check(a, oracle_mod.xcorr(x, ns, npol), "super-ci8-extreme")
+    b, _ = run_xeng(x, ns, npol, "ci8", "i8", tile=128)
+    assert np.array_equal(a, b)
+
+
+def test_super_ci8_windows():
+    """Two int32 windows (66572 samples each at the default bound) summed into the int64
+    totals equal, exactly, the two halves run as single-window jobs."""
+    from paper_1107_4264_amd import xcorr as X
+
+    ns, npol, F, T1, T2 = 256, 2, 1, 66572, 200
+    p = X.xcorr_plan(ns, npol, F, T1 + T2, X.IN_CI8, X.ACC_I8_MMA_I32, 0, 512)
+    assert p["nwindows"] == 2 and p["out_dtype"] == X.OUT_CI64
+    x = synth.voltages_np(synth.SEED_BASE + 72, T1 + T2, F, ns * npol, ("uniform", -127, 127))
+    say("super ci8 windows", T1 + T2)
+    full, ot = run_xeng(x, ns, npol, "ci8", "i8", tile=512)
+    assert ot == X.OUT_CI64
+    a, _ = run_xeng(x[:T1], ns, npol, "ci8", "i8", tile=512)
+    b, _ = run_xeng(x[T1:], ns, npol, "ci8", "i8", tile=512)
+    assert np.array_equal(as_exact_int(full), as_exact_int(a) + as_exact_int(b))
