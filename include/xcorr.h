@@ -198,15 +198,16 @@ int xcorr_batch_set_max_abs(xcorr_batch_t *b, int max_abs);
 
 /* in[j], out[j]: device buffers of job j (host arrays of njobs device pointers).  Enqueues
  * on `stream`: a small upload of the job table, zero fills of the outputs that sum several
- * windows, one whole-channel launch per job that the planner gives that kernel (see
- * xcorr_set_tile), and one persistent launch of the tiled kernel over the work items of
- * all other jobs.  May wait on the host for the previous run's table upload to finish. */
+ * windows, the launches of each job that the planner gives the whole-channel or the
+ * super-tiled kernel (see xcorr_set_tile), and one persistent launch of the tiled kernel
+ * over the work items of all other jobs.  May wait on the host for the previous run's table upload to finish. */
 int xcorr_batch_run(xcorr_batch_t *b, const void *const *in, void *const *out, hipStream_t stream);
 
 size_t xcorr_batch_in_bytes(const xcorr_batch_t *b, int job);
 size_t xcorr_batch_out_bytes(const xcorr_batch_t *b, int job);
 int xcorr_batch_out_type(const xcorr_batch_t *b, int job);
-/* Work items of the persistent tiled launch (jobs on the whole-channel kernel excluded). */
+/* Work items of the persistent tiled launch (jobs on the whole-channel or super-tiled
+ * kernels excluded). */
 int64_t xcorr_batch_items(const xcorr_batch_t *b);
 void xcorr_batch_destroy(xcorr_batch_t *b);
 

@@ -416,12 +416,13 @@ int batch_plan(xcorr_batch *b, int max_abs)
         const int rc = make_plan(jb.nstation, jb.npol, jb.nchan, jb.ntime, b->in_fmt, b->acc, ma, tile, &plans[j], &err);
         if (rc) return fail(rc, "job " + std::to_string(j) + ": " + err);
         if (b->acc == ACC_F8 && b->in_fmt == IN_CI8 && max_abs == 0) plans[j].max_abs = 128;
-        // jobs the planner gives the whole-channel kernel run it (one launch each); the
-        // others share the persistent launch of the tiled kernel
+        // jobs the planner gives the whole-channel or the super-tiled kernel run it (their
+        // own persistent launches); the others share the persistent launch of the tiled
+        // kernel
         Plan wp;
         if (b->acc != ACC_F32_CMAC &&
             make_plan(jb.nstation, jb.npol, jb.nchan, jb.ntime, b->in_fmt, b->acc, ma, 0, &wp, &err) == XCORR_OK &&
-            wp.tile == CHAN_TILE) {
+            (wp.tile == CHAN_TILE || wp.tile == SUPER_TILE)) {
             wp.max_abs = plans[j].max_abs;
             plans[j] = wp;
             whole[j] = 1;
@@ -577,7 +578,7 @@ int xcorr_batch_run(xcorr_batch_t *b, const void *const *in, void *const *out, h
     for (int j = 0; j < njobs; ++j)
         if (b->whole[j]) {
             rc = launch_job(b->plans[j], job_from_plan(b->plans[j], in[j], out[j]), stream);
-            if (rc) return hip_fail(rc, "whole-channel launch of a batch job");
+            if (rc) return hip_fail(rc, "whole-channel / super-tile launch of a batch job");
         }
     if (b->nitems == 0) return XCORR_OK;
     rc = b->acc == ACC_F32_CMAC

@@ -76,3 +76,34 @@ def test_batch_ci4(oracle_mod):
         for k, (o, want) in enumerate(zip(outs, wants)):
             assert np.array_equal(as_exact_int(o.cpu().numpy()), want), f"{acc} job {k}"
         b.close()
+
+
+def test_batch_mixed_kernels(oracle_mod):
+    """One batch whose jobs run on three kernels: a 512-input job (super-tiles), a
+    256-input job (whole channel) and small jobs (the persistent tiled launch), for 8-bit
+    samples on the int8 path and 4-bit samples on the int8 and fp8 paths."""
+    import torch
+
+    from paper_1107_4264_amd import xcorr as X
+
+    dev = device()
+    for fmt, accs in (("ci8", ["i8"]), ("ci4", ["i8", "f8"])):
+        jobs = [(256, 2, 2, 70), (128, 2, 3, 50), (21, 2, 2, 40), (5, 1, 3, 9)]
+        xs, wants = [], []
+        for k, (ns, npol, F, T) in enumerate(jobs):
+            if fmt == "ci8":
+                x = synth.voltages_np(880 + k, T, F, ns * npol, ("gauss", 30.0, 127))
+                xs.append(x)
+                wants.append(oracle_mod.xcorr(x, ns, npol))
+            else:
+                p = synth.pack_ci4(synth.voltages_np(890 + k, T, F, ns * npol, ("uniform", -8, 7)))
+                xs.append(p)
+                wants.append(oracle_mod.xcorr(p, ns, npol, fmt=oracle_mod.CI4))
+        for acc in accs:
+            say("batch mixed", fmt, acc)
+            b = X.Batch(jobs, fmt, acc)
+            outs = b.run([torch.from_numpy(np.ascontiguousarray(x)).to(dev) for x in xs])
+            torch.cuda.synchronize()
+            for k, (o, want) in enumerate(zip(outs, wants)):
+                assert np.array_equal(as_exact_int(o.cpu().numpy()), want), f"{fmt} {acc} job {k}"
+            b.close()
