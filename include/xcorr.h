@@ -117,8 +117,9 @@ xcorr_handle_t *xcorr_create(int nstation, int npol, int nchan, int ntime,
 int xcorr_set_max_abs(xcorr_handle_t *h, int max_abs);
 
 /* Choose the kernel shape (Sec. 4.2's tiling of the triangle, re-planned for gfx950):
- *   0    automatic (the default): 512 when allowed, else 256 when allowed and nin > 192,
- *        else 128 (64 when nin <= 64; always 64 for F32_CMAC);
+ *   0    automatic (the default): 512 when allowed and its padded last super-row costs at
+ *        most 15 % more computed blocks than 128-tiles, else 256 when allowed and
+ *        nin > 192, else 128 (64 when nin <= 64; always 64 for F32_CMAC);
  *   64, 128  square tiles of that many inputs, one workgroup per (channel, tile, window);
  *   256  whole channel: one persistent workgroup per compute unit holds the triangle of a
  *        channel and reads every sample once; needs CI8 input, the int8 or fp16 path and
@@ -127,7 +128,7 @@ int xcorr_set_max_abs(xcorr_handle_t *h, int max_abs);
  *   512  super-tiles: the triangle of each channel cut into 256-input triangles and
  *        256 x 128 rectangles, each held by one persistent workgroup (two launches); needs
  *        CI4 input on the int8 or fp8 path, or CI8 input on the int8 path, and nin a
- *        multiple of 256 in 512..2048; for CI4 on the int8 path also
+ *        multiple of 16 in 272..2048; for CI4 on the int8 path also
  *        ntime <= (2^31 - 1) / (128 max_abs^2) (its operands are the samples times 8).
  *        Same alignment fallback.
  * All shapes give bit-identical visibilities.  XCORR_ERR_INVALID_ARG for a shape the job

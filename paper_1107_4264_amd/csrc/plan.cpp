@@ -78,7 +78,7 @@ bool chan_kernel_ok(int nin, int in_fmt, int acc)
 bool super_kernel_ok(int nin, int nchan, int64_t ntime, int in_fmt, int acc, int max_abs)
 {
     const bool fmt_ok = (in_fmt == IN_CI4 && (acc == ACC_I8 || acc == ACC_F8)) || (in_fmt == IN_CI8 && acc == ACC_I8);
-    if (!fmt_ok || nin % 256 != 0 || nin < 512 || nin > 2048) return false;
+    if (!fmt_ok || nin % 16 != 0 || nin <= 256 || nin > 2048) return false;
     // the copy offsets of a block (32 rows) stay below 2^32 bytes
     if (32 * (int64_t)nchan * nin * (int64_t)in_sample_bytes(in_fmt) >= ((int64_t)1 << 32)) return false;
     // fp8 operands and int8 operands from 8-bit samples are the samples themselves (the
@@ -95,7 +95,7 @@ int64_t computed_pairs_per_sample(int nin, int tile, int acc)
     if (tile == CHAN_TILE) return 36 * 32 * 32;
     // super-tiles: S triangles of 36 blocks and S (S - 1) rectangles of 32 blocks
     if (tile == SUPER_TILE) {
-        const int64_t s = nin / 256;
+        const int64_t s = (nin + 255) / 256;
         return (s * 36 + s * (s - 1) * 32) * 32 * 32;
     }
     const int64_t nts = (nin + tile - 1) / tile;
@@ -161,10 +161,14 @@ int make_plan(int nstation, int npol, int nchan, int ntime, int in_fmt, int acc,
     // Above 192 inputs the whole-channel kernel computes at most 36/28 of the useful blocks
     // and reads every sample once, in whole rows.
     if (chan_kernel_ok(p.nin, in_fmt, acc) && p.nin > 192) tile = CHAN_TILE;
-    // From 512 inputs (a multiple of 256) of 4-bit samples on the int8 / fp8 paths and of
-    // 8-bit samples on the int8 path, super-tiles: whole 256-input pieces per workgroup,
-    // operands widened (or moved) once per block in LDS.
-    if (super_kernel_ok(p.nin, nchan, ntime, in_fmt, acc, max_abs)) tile = SUPER_TILE;
+    // Above 256 inputs of 4-bit samples on the int8 / fp8 paths and of 8-bit samples on the
+    // int8 path, super-tiles (whole 256-input pieces per workgroup, operands widened or moved
+    // once per block in LDS) when their padding of the last super-row costs at most 15 %
+    // more computed blocks than 128-tiles (equal at multiples of 256; the pieces run
+    // 1.15-1.3x faster per block).
+    if (super_kernel_ok(p.nin, nchan, ntime, in_fmt, acc, max_abs) &&
+        computed_pairs_per_sample(p.nin, SUPER_TILE, acc) * 100 <= computed_pairs_per_sample(p.nin, 128, acc) * 115)
+        tile = SUPER_TILE;
     if (tile_override) {
         bool ok;
         if (acc == ACC_F32_CMAC) ok = tile_override == 64;
@@ -184,7 +188,7 @@ int make_plan(int nstation, int npol, int nchan, int ntime, int in_fmt, int acc,
     }
     p.tile = tile;
     if (tile == SUPER_TILE) {
-        p.ntile_side = p.nin / 256;                        // super-rows
+        p.ntile_side = (p.nin + 255) / 256;                // super-rows
         p.tiles_per_chan = p.ntile_side * p.ntile_side;    // triangles + rectangles
     } else {
         p.ntile_side = tile == CHAN_TILE ? 1 : (p.nin + tile - 1) / tile;

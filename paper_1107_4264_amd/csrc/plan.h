@@ -36,11 +36,12 @@ constexpr int CHAN_TILE = 256;
 bool chan_kernel_ok(int nin, int in_fmt, int acc);
 
 // Tile value of the super-tiled kernel: 256-input triangles and 256 x 128 rectangles of
-// arrays of 512..2048 inputs, 4-bit samples, int8 and fp8 paths.
+// arrays of 272..2048 inputs (4-bit samples on the int8 and fp8 paths, 8-bit samples on the
+// int8 path).
 constexpr int SUPER_TILE = 512;
 
 // Whether the super-tiled kernel accepts a job: CI4 samples on the int8 or fp8 path or CI8
-// samples on the int8 path, nin a multiple of 256 in 512..2048; for CI4 on the int8 path
+// samples on the int8 path, nin a multiple of 16 in 272..2048; for CI4 on the int8 path
 // also one window of its scaled operands (floor((2^31-1)/(128 m^2)) samples for samples
 // bounded by m).
 bool super_kernel_ok(int nin, int nchan, int64_t ntime, int in_fmt, int acc, int max_abs);

@@ -1,6 +1,6 @@
-// Super-tiled X-engine on the CDNA4 matrix cores (gfx950) for arrays of 256 S inputs
-// (S = 2..8): 4-bit complex samples on the int8 and fp8 paths, 8-bit samples on the int8
-// path.
+// Super-tiled X-engine on the CDNA4 matrix cores (gfx950) for arrays of 272..2048 inputs
+// (a multiple of 16; S = ceil(nin / 256) super-rows, the last one possibly partial): 4-bit
+// complex samples on the int8 and fp8 paths, 8-bit samples on the int8 path.
 //
 // A channel's triangle (Eq. 4) is cut into S diagonal triangles of 256 inputs (the 36-block
 // work lists of the whole-channel kernel) and S (S - 1) rectangles of 256 row inputs x 128
@@ -201,11 +201,15 @@ __device__ __forceinline__ void run_wave_super(const XJob &p, int lane)
     for (int m = 0; m < NAW; ++m)
         voff_a[m] = (uint32_t)(((8 * m + W) * (1024 / Gs::AROW) + lane / LA) * row_stride + 16 * (lane % LA));
     const uint32_t voff_b = (uint32_t)((ib * (1024 / Gs::BROW) + lane / LB) * row_stride + 16 * (lane % LB));
+    // The last super-row may be partial (nin not a multiple of 256): its chunks past the
+    // last input read zeros (the rows below would otherwise hold the next channel).
     auto issue = [&](const SCursor<TRI> &c, int slot, int m) __attribute__((always_inline)) {
         const uint32_t sb = lds0 + slot * Gs::RAW;
-        if (m < NAW)
-            dma16(seg_rsrc(p, c, c.seg_a, Gs::AROW, row_stride, Gs::BPS), sb + (8 * m + W) * 1024, voff_a[m]);
-        else
+        if (m < NAW) {
+            const int va = min(Gs::AROW, (p.nin - c.seg_a) * Gs::BPS);  // valid bytes of a row
+            const uint32_t vo = 16 * (lane % LA) < va ? voff_a[m] : COOB;
+            dma16(seg_rsrc(p, c, c.seg_a, va, row_stride, Gs::BPS), sb + (8 * m + W) * 1024, vo);
+        } else
             dma16(seg_rsrc(p, c, c.seg_b, TRI ? 0 : Gs::BROW, row_stride, Gs::BPS), sb + SP_TB * Gs::AROW + ib * 1024,
                   voff_b);
     };

@@ -245,8 +245,8 @@ def test_super_tile_plan():
 
 
 @pytest.mark.parametrize("args", [
-    (128, 2, 4, 100, "IN_CI4", "ACC_I8_MMA_I32"),   # 256 inputs: below 512
-    (200, 2, 4, 100, "IN_CI4", "ACC_I8_MMA_I32"),   # 400 inputs: not a multiple of 256
+    (128, 2, 4, 100, "IN_CI4", "ACC_I8_MMA_I32"),   # 256 inputs: one super-row
+    (204, 2, 4, 100, "IN_CI4", "ACC_I8_MMA_I32"),   # 408 inputs: not a multiple of 16
     (1280, 2, 4, 100, "IN_CI4", "ACC_I8_MMA_I32"),  # 2560 inputs: above 2048
     (256, 2, 4, 100, "IN_CI8", "ACC_F16_MMA_F32"),  # 8-bit samples on the fp16 path
     (256, 2, 4, 100, "IN_CI4", "ACC_F16_MMA_F32"),  # fp16 path
@@ -274,3 +274,18 @@ def test_super_tile_ci8():
     assert p["nwindows"] == 2 and p["out_dtype"] == X.OUT_CI64
     with pytest.raises(X.XcorrError):
         X.xcorr_plan(256, 2, 4, 100, X.IN_CI8, X.ACC_F16_MMA_F32, 0, 512)
+
+
+def test_super_tile_ragged():
+    # any multiple of 16 above 256: the last super-row is partial (padded with zero inputs)
+    p = X.xcorr_plan(200, 2, 3, 100, X.IN_CI4, X.ACC_I8_MMA_I32, 0, 512)
+    assert p["ntile_side"] == 2 and p["tiles_per_chan"] == 4
+    assert p["computed_cmacs"] == (2 * 36 + 2 * 32) * 1024 * 3 * 100
+    # automatic choice: super-tiles only when the padding costs <= 15 % more blocks than
+    # 128-tiles: 496 / 752 / 1008 inputs (last 32-block of a super-row) yes, 272 / 400 no
+    def auto(nin, fmt=X.IN_CI4, acc=X.ACC_I8_MMA_I32):
+        return X.xcorr_plan(nin // 2, 2, 3, 100, fmt, acc, 0)["tile"]
+
+    assert auto(496) == 512 and auto(752) == 512 and auto(1008) == 512
+    assert auto(496, X.IN_CI8) == 512 and auto(496, acc=X.ACC_F8E4M3_MMA_F32) == 512
+    assert auto(272) == 128 and auto(400) == 128 and auto(784) == 128

@@ -195,3 +195,23 @@ def test_super_ci8_windows():
     a, _ = run_xeng(x[:T1], ns, npol, "ci8", "i8", tile=512)
     b, _ = run_xeng(x[T1:], ns, npol, "ci8", "i8", tile=512)
     assert np.array_equal(as_exact_int(full), as_exact_int(a) + as_exact_int(b))
+
+
+
+@pytest.mark.parametrize("fmt_acc", [("ci4", "i8"), ("ci4", "f8"), ("ci8", "i8")], ids=lambda t: "-".join(t))
+@pytest.mark.parametrize("shape", [(136, 2, 2, 45), (200, 2, 2, 37), (392, 2, 1, 33), (304, 1, 2, 40)],
+                         ids=lambda s: "x".join(map(str, s)))
+def test_super_ragged(oracle_mod, fmt_acc, shape):
+    """Arrays that are not a multiple of 256 inputs (272, 400, 784 and 304 single
+    polarisation): the last super-row is partial; its missing inputs read as zeros."""
+    fmt, acc = fmt_acc
+    ns, npol, F, T = shape
+    if fmt == "ci4":
+        x = synth.pack_ci4(synth.voltages_np(synth.SEED_BASE + 80 + ns, T, F, ns * npol, ("uniform", -8, 7)))
+        want = oracle_mod.xcorr(x, ns, npol, fmt=oracle_mod.CI4)
+    else:
+        x = synth.voltages_np(synth.SEED_BASE + 81 + ns, T, F, ns * npol, ("gauss", 40.0, 127))
+        want = oracle_mod.xcorr(x, ns, npol)
+    say("super ragged", fmt, acc, shape)
+    got, _ = run_xeng(x, ns, npol, fmt, acc, tile=512)
+    _check(got, want, f"super-ragged/{fmt}/{acc}/{shape}")
