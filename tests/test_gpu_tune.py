@@ -43,3 +43,31 @@ def test_autotune_picks_a_shape_and_keeps_bits(oracle_mod, acc):
         c2.close()
     finally:
         X.xcorr_autotune_clear()
+
+
+@pytest.mark.parametrize("acc", ["i8", "f8"])
+def test_autotune_includes_super_tiles(oracle_mod, acc):
+    """A 4-bit job of 512 inputs: the candidates include super-tiles (512), 128 and 64;
+    whichever wins, the visibilities are the oracle's."""
+    import torch
+
+    from paper_1107_4264_amd import xcorr as X
+
+    dev = device()
+    ns, npol, F, T = 256, 2, 6, 200
+    packed = synth.pack_ci4(synth.voltages_np(synth.SEED_BASE + 61, T, F, ns * npol, ("uniform", -8, 7)))
+    xt = torch.from_numpy(packed).to(dev)
+    X.xcorr_autotune_clear()
+    try:
+        c = X.Correlator(ns, npol, F, T, "ci4", acc)
+        assert c.tile == 512
+        out = c.empty_out(dev)
+        tile = c.autotune(xt, out, reps=2)
+        torch.cuda.synchronize()
+        say("autotune ci4", acc, "tile", tile)
+        assert tile in (64, 128, 512) and c.tile == tile
+        want = oracle_mod.xcorr(packed, ns, npol, fmt=oracle_mod.CI4)
+        assert np.array_equal(as_exact_int(out.cpu().numpy()), want)
+        c.close()
+    finally:
+        X.xcorr_autotune_clear()
