@@ -47,7 +47,8 @@
  * a run of several windows sums the windows on the GPU into ci64 or c128.  max_abs defaults
  * to 127 for CI8 on the int8 path, 128 for CI8 on the other paths and 8 for CI4;
  * xcorr_set_max_abs declares a smaller bound on the data (a promise by the caller, not
- * checked).  CF32 input always runs one window and writes c64.
+ * checked).  CF32 input runs one window and writes c64 unless xcorr_set_window asks for
+ * shorter windows.
  *
  * Ownership and ordering.  Input and output are device pointers owned by the caller and
  * must stay valid until the work enqueued on `stream` has completed.  Every run is
@@ -128,8 +129,8 @@ int xcorr_set_max_abs(xcorr_handle_t *h, int max_abs);
  *   512  super-tiles: the triangle of each channel cut into 256-input triangles and
  *        256 x 128 rectangles, each held by one persistent workgroup (two launches); needs
  *        CI4 input on the int8 or fp8 path, or CI8 input on the int8 path, and nin a
- *        multiple of 16 in 272..2048; for CI4 on the int8 path also
- *        ntime <= (2^31 - 1) / (128 max_abs^2) (its operands are the samples times 8).
+ *        multiple of 16 in 272..2048; for CI4 on the int8 path also windows of at most
+ *        (2^31 - 1) / (128 max_abs^2) samples (its operands are the samples times 8).
  *        Same alignment fallback.
  * All shapes give bit-identical visibilities.  XCORR_ERR_INVALID_ARG for a shape the job
  * does not allow (the handle keeps its previous shape). */
@@ -137,6 +138,15 @@ int xcorr_set_tile(xcorr_handle_t *h, int tile);
 
 /* The kernel shape the handle runs (64, 128, 256 or 512), or an error code. */
 int xcorr_get_tile(const xcorr_handle_t *h);
+
+/* Accumulation window (the dump interval of Sec. 2.3's wider accumulators): integrate in
+ * windows of `window` samples, each summed into the wide output (ci64 / c128) when the run
+ * has more than one.  0 (the default) takes the longest exact window (see the exactness
+ * note above); a positive value must not exceed xcorr_window_limit for the handle's
+ * format, path and max_abs (XCORR_ERR_UNSUPPORTED otherwise: the sums would not be exact).
+ * Shorter windows give the same visibilities; they only add window sums.  A later
+ * xcorr_set_max_abs keeps the requested window.  XCORR_ERR_INVALID_ARG for window < 0. */
+int xcorr_set_window(xcorr_handle_t *h, int window);
 
 /* Autotuner (the tile-size search of Sec. 4.2 / 6, done on the device): run every kernel
  * shape the job allows `reps` times (after one warm-up) on `in` / `out` on `stream`, timed
@@ -223,9 +233,17 @@ void xcorr_batch_destroy(xcorr_batch_t *b);
  * int64 / fp64.
  *
  * The stream owns a copy stream (default priority), two device chunk buffers and their
- * events.  Host chunks should be pinned (hipHostMalloc) for the copies to be asynchronous;
- * a chunk passed to xcorr_stream_push must stay unchanged until the push after next has
- * returned or xcorr_stream_end has been called and `stream` synchronised.
+ * events.  Host chunks should be pinned (hipHostMalloc) for the copies to be asynchronous.
+ * Release point: a chunk passed to push p may be changed or freed by the caller once push
+ * p + 2 has returned (push p + 2 waits on the host for the copy of chunk p to finish, as
+ * Algorithm 1 synchronises each iteration), or once xcorr_stream_end has been called and
+ * `stream` synchronised.  Pushes recorded by xcorr_stream_capture do not wait.
+ *
+ * Differences from a create(total_ntime, dump_every) / push / finish interface: the
+ * integration length is the number of pushes between begin and end (any number), and the
+ * int32 / fp32 accumulators are dumped into the wide totals at the end of every chunk and,
+ * within a chunk, every xcorr_stream_set_window samples (default: the longest exact
+ * window).
  */
 typedef struct xcorr_stream xcorr_stream_t;
 
@@ -234,6 +252,10 @@ xcorr_stream_t *xcorr_stream_create(int nstation, int npol, int nchan, int chunk
 
 /* As xcorr_set_max_abs, for every chunk; call before xcorr_stream_begin. */
 int xcorr_stream_set_max_abs(xcorr_stream_t *s, int max_abs);
+
+/* As xcorr_set_window, within every chunk (dumps also happen at every chunk end); call
+ * before xcorr_stream_begin. */
+int xcorr_stream_set_window(xcorr_stream_t *s, int window);
 
 /* Start an integration into `out` (device, xcorr_stream_out_bytes, type
  * xcorr_stream_out_type): zero it on `stream`. */
@@ -290,9 +312,9 @@ typedef struct {
 } xcorr_plan_info;
 
 /* Plan a job as xcorr_create + xcorr_set_max_abs (max_abs 0: the default) +
- * xcorr_set_tile (tile 0: automatic) would. */
+ * xcorr_set_tile (tile 0: automatic) + xcorr_set_window (window 0: longest exact) would. */
 int xcorr_plan(int nstation, int npol, int nchan, int ntime, xcorr_in_dtype in_dtype,
-               xcorr_acc_dtype acc_dtype, int max_abs, int tile, xcorr_plan_info *info);
+               xcorr_acc_dtype acc_dtype, int max_abs, int tile, int window, xcorr_plan_info *info);
 
 /* Largest window (samples) for which the accumulators of acc_dtype stay exact with
  * components bounded by max_abs; < 0 on a bad argument. */

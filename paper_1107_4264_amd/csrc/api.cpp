@@ -89,7 +89,8 @@ int launch_job(const Plan &pl, XJob j, hipStream_t stream)
         // the row copies need 16-byte aligned rows: run 128-tiles instead
         Plan tp;
         std::string err;
-        if (make_plan(pl.nstation, pl.npol, pl.nchan, pl.ntime, pl.in_fmt, pl.acc, pl.max_abs, 128, &tp, &err))
+        if (make_plan(pl.nstation, pl.npol, pl.nchan, pl.ntime, pl.in_fmt, pl.acc, pl.max_abs, 128, &tp, &err,
+                      pl.window_req))
             return (int)hipErrorInvalidValue;
         XJob tj = job_from_plan(tp, j.in, j.out);
         tj.accumulate = j.accumulate;
@@ -138,7 +139,8 @@ void apply_tuned(Plan &p)
     if (t == 0 || t == p.tile) return;
     Plan q;
     std::string err;
-    if (make_plan(p.nstation, p.npol, p.nchan, p.ntime, p.in_fmt, p.acc, p.max_abs, t, &q, &err) == XCORR_OK) {
+    if (make_plan(p.nstation, p.npol, p.nchan, p.ntime, p.in_fmt, p.acc, p.max_abs, t, &q, &err, p.window_req) ==
+        XCORR_OK) {
         q.max_abs = p.max_abs;
         p = q;
     }
@@ -188,12 +190,13 @@ static int plan_info_fill(const Plan &p, xcorr_plan_info *info)
 }
 
 int xcorr_plan(int nstation, int npol, int nchan, int ntime, xcorr_in_dtype in_dtype,
-               xcorr_acc_dtype acc_dtype, int max_abs, int tile, xcorr_plan_info *info)
+               xcorr_acc_dtype acc_dtype, int max_abs, int tile, int window, xcorr_plan_info *info)
 {
     if (!info) return fail(XCORR_ERR_INVALID_ARG, "null info");
     Plan p;
     std::string err;
-    const int rc = make_plan(nstation, npol, nchan, ntime, (int)in_dtype, (int)acc_dtype, max_abs, tile, &p, &err);
+    const int rc =
+        make_plan(nstation, npol, nchan, ntime, (int)in_dtype, (int)acc_dtype, max_abs, tile, &p, &err, window);
     if (rc) return fail(rc, err);
     return plan_info_fill(p, info);
 }
@@ -237,7 +240,8 @@ int xcorr_set_max_abs(xcorr_handle_t *h, int max_abs)
     Plan p;
     std::string err;
     const Plan &o = h->plan;
-    const int rc = make_plan(o.nstation, o.npol, o.nchan, o.ntime, o.in_fmt, o.acc, max_abs, o.tile, &p, &err);
+    const int rc = make_plan(o.nstation, o.npol, o.nchan, o.ntime, o.in_fmt, o.acc, max_abs, o.tile, &p, &err,
+                             o.window_req);
     if (rc) return fail(rc, err);
     apply_tuned(p);
     h->plan = p;
@@ -254,7 +258,8 @@ int xcorr_autotune(xcorr_handle_t *h, const void *in, void *out, hipStream_t str
     for (int t : {SUPER_TILE, CHAN_TILE, 128, 64}) {
         Plan q;
         std::string err;
-        if (make_plan(o.nstation, o.npol, o.nchan, o.ntime, o.in_fmt, o.acc, o.max_abs, t, &q, &err) == XCORR_OK) {
+        if (make_plan(o.nstation, o.npol, o.nchan, o.ntime, o.in_fmt, o.acc, o.max_abs, t, &q, &err, o.window_req) ==
+            XCORR_OK) {
             q.max_abs = o.max_abs;
             cand.push_back(q);
         }
@@ -332,8 +337,29 @@ int xcorr_set_tile(xcorr_handle_t *h, int tile)
     Plan p;
     std::string err;
     const Plan &o = h->plan;
-    const int rc = make_plan(o.nstation, o.npol, o.nchan, o.ntime, o.in_fmt, o.acc, o.max_abs, tile, &p, &err);
+    const int rc =
+        make_plan(o.nstation, o.npol, o.nchan, o.ntime, o.in_fmt, o.acc, o.max_abs, tile, &p, &err, o.window_req);
     if (rc) return fail(rc, err);
+    h->plan = p;
+    return XCORR_OK;
+}
+
+int xcorr_set_window(xcorr_handle_t *h, int window)
+{
+    if (!h) return fail(XCORR_ERR_INVALID_ARG, "null handle");
+    Plan p;
+    std::string err;
+    const Plan &o = h->plan;
+    // an fp8 job over 8-bit samples without a declared bound plans with the fp8 bound and
+    // stays refused at run time (see xcorr_create)
+    const bool undeclared = o.acc == ACC_F8 && o.in_fmt == IN_CI8 && o.max_abs > 16;
+    const int ma = undeclared ? 16 : o.max_abs;
+    // keep a tile the caller or the autotuner chose, unless the new windows rule it out
+    int rc = make_plan(o.nstation, o.npol, o.nchan, o.ntime, o.in_fmt, o.acc, ma, o.tile, &p, &err, window);
+    if (rc == XCORR_ERR_INVALID_ARG && window >= 0)
+        rc = make_plan(o.nstation, o.npol, o.nchan, o.ntime, o.in_fmt, o.acc, ma, 0, &p, &err, window);
+    if (rc) return fail(rc, err);
+    if (undeclared) p.max_abs = o.max_abs;
     h->plan = p;
     return XCORR_OK;
 }
@@ -627,6 +653,7 @@ struct xcorr_stream {
     hipEvent_t consumed[2] = {nullptr, nullptr};
     hipEvent_t began = nullptr;
     bool consumed_valid[2] = {false, false};
+    bool copied_valid[2] = {false, false};  // copied[k] records an eager (not captured) copy
     void *out = nullptr;
     int64_t npush = 0;
 };
@@ -710,8 +737,25 @@ int xcorr_stream_set_max_abs(xcorr_stream_t *s, int max_abs)
     Plan p;
     std::string err;
     const Plan &o = s->plan;
-    const int rc = make_plan(o.nstation, o.npol, o.nchan, o.ntime, o.in_fmt, o.acc, max_abs, o.tile, &p, &err);
+    const int rc = make_plan(o.nstation, o.npol, o.nchan, o.ntime, o.in_fmt, o.acc, max_abs, o.tile, &p, &err,
+                             o.window_req);
     if (rc) return fail(rc, err);
+    s->plan = p;
+    return XCORR_OK;
+}
+
+int xcorr_stream_set_window(xcorr_stream_t *s, int window)
+{
+    if (!s) return fail(XCORR_ERR_INVALID_ARG, "null stream object");
+    if (s->out) return fail(XCORR_ERR_INVALID_ARG, "an integration is in progress");
+    Plan p;
+    std::string err;
+    const Plan &o = s->plan;
+    const bool undeclared = o.acc == ACC_F8 && o.in_fmt == IN_CI8 && o.max_abs > 16;
+    const int ma = undeclared ? 16 : o.max_abs;
+    const int rc = make_plan(o.nstation, o.npol, o.nchan, o.ntime, o.in_fmt, o.acc, ma, 0, &p, &err, window);
+    if (rc) return fail(rc, err);
+    if (undeclared) p.max_abs = o.max_abs;
     s->plan = p;
     return XCORR_OK;
 }
@@ -731,6 +775,7 @@ int xcorr_stream_begin(xcorr_stream_t *s, void *out, hipStream_t stream)
     s->out = out;
     s->npush = 0;
     s->consumed_valid[0] = s->consumed_valid[1] = false;
+    s->copied_valid[0] = s->copied_valid[1] = false;
     return XCORR_OK;
 }
 
@@ -740,6 +785,18 @@ int xcorr_stream_push(xcorr_stream_t *s, const void *host_chunk, hipStream_t str
     if (!s->out) return fail(XCORR_ERR_INVALID_ARG, "xcorr_stream_begin was not called");
     const int slot = (int)(s->npush & 1);
     hipError_t e;
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if ((e = hipStreamIsCapturing(stream, &cap)) != hipSuccess) return hip_fail((int)e, "capture status");
+    const bool eager = cap == hipStreamCaptureStatusNone;
+    // Release point of the host chunks: push p waits on the host for the copy of chunk
+    // p - 2 (the last copy through this slot), so once push p returns the caller may reuse
+    // chunk p - 2 (Algorithm 1 synchronises every iteration for the same reason).  The copy
+    // queue is one chunk deep by then, so the wait costs no overlap.  Copies recorded into a
+    // graph are not waited for here (each launch of the graph orders its own copies).
+    if (eager && s->copied_valid[slot]) {
+        if ((e = hipEventSynchronize(s->copied[slot])) != hipSuccess) return hip_fail((int)e, "chunk release wait");
+        s->copied_valid[slot] = false;
+    }
     // the copy into this buffer waits for the kernel that last read it (or for the start
     // of the integration); the kernel waits for the copy
     e = hipStreamWaitEvent(s->copy_stream, s->consumed_valid[slot] ? s->consumed[slot] : s->began, 0);
@@ -749,6 +806,7 @@ int xcorr_stream_push(xcorr_stream_t *s, const void *host_chunk, hipStream_t str
         if (e != hipSuccess) return hip_fail((int)e, "chunk copy");
     }
     if ((e = hipEventRecord(s->copied[slot], s->copy_stream)) != hipSuccess) return hip_fail((int)e, "copy event");
+    s->copied_valid[slot] = eager;
     if ((e = hipStreamWaitEvent(stream, s->copied[slot], 0)) != hipSuccess) return hip_fail((int)e, "compute wait");
     XJob j = job_from_plan(s->plan, s->dbuf[slot], s->out);
     j.accumulate = 1;  // add into the wide totals

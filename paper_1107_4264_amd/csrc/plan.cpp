@@ -75,18 +75,18 @@ bool chan_kernel_ok(int nin, int in_fmt, int acc)
     return in_fmt == IN_CI8 && (acc == ACC_I8 || acc == ACC_F16) && nin % 8 == 0 && nin >= 1 && nin <= CHAN_TILE;
 }
 
-bool super_kernel_ok(int nin, int nchan, int64_t ntime, int in_fmt, int acc, int max_abs)
+bool super_kernel_ok(int nin, int nchan, int64_t window, int in_fmt, int acc, int max_abs)
 {
     const bool fmt_ok = (in_fmt == IN_CI4 && (acc == ACC_I8 || acc == ACC_F8)) || (in_fmt == IN_CI8 && acc == ACC_I8);
     if (!fmt_ok || nin % 16 != 0 || nin <= 256 || nin > 2048) return false;
     // the copy offsets of a block (32 rows) stay below 2^32 bytes
     if (32 * (int64_t)nchan * nin * (int64_t)in_sample_bytes(in_fmt) >= ((int64_t)1 << 32)) return false;
     // fp8 operands and int8 operands from 8-bit samples are the samples themselves (the
-    // usual windows); int8 operands from 4-bit samples are 8 x the samples, so the whole job
-    // must fit one int32 window of the scaled sums
+    // usual windows); int8 operands from 4-bit samples are 8 x the samples, so every window
+    // must stay within the int32 limit of the scaled sums
     if (acc == ACC_F8 || in_fmt == IN_CI8) return true;
     const int64_t m = max_abs;
-    return m >= 1 && ntime <= (int64_t)2147483647 / (128 * m * m);
+    return m >= 1 && window <= (int64_t)2147483647 / (128 * m * m);
 }
 
 int64_t computed_pairs_per_sample(int nin, int tile, int acc)
@@ -116,7 +116,7 @@ int64_t computed_pairs_per_sample(int nin, int tile, int acc)
 }
 
 int make_plan(int nstation, int npol, int nchan, int ntime, int in_fmt, int acc, int max_abs,
-              int tile_override, Plan *pl, std::string *err)
+              int tile_override, Plan *pl, std::string *err, int window_req)
 {
     if (!pl) {
         *err = "null plan";
@@ -133,6 +133,10 @@ int make_plan(int nstation, int npol, int nchan, int ntime, int in_fmt, int acc,
     if (in_fmt == IN_CF32 && acc != ACC_F32_CMAC) {
         *err = "float input is only accepted by the FP32 CMAC path";
         return XCORR_ERR_UNSUPPORTED;
+    }
+    if (window_req < 0) {
+        *err = "window must be >= 0 (0: the longest exact window)";
+        return XCORR_ERR_INVALID_ARG;
     }
     const int64_t nin64 = (int64_t)nstation * npol;
     if (nin64 > 65536) {
@@ -156,7 +160,26 @@ int make_plan(int nstation, int npol, int nchan, int ntime, int in_fmt, int acc,
     p.in_fmt = in_fmt;
     p.acc = acc;
     p.max_abs = in_fmt == IN_CF32 ? 0 : max_abs;
+    p.window_req = window_req;
     p.nin = (int)nin64;
+
+    // Accumulation windows (Sec. 2.3: accumulators wider than the data): the longest exact
+    // window, rounded down to whole 64-sample blocks, or the caller's shorter one.
+    const int64_t lim = window_limit(in_fmt, acc, in_fmt == IN_CF32 ? 1 : max_abs);
+    if (window_req > 0 && window_req > lim) {
+        *err = "window longer than the exact limit of the accumulators (see xcorr_window_limit)";
+        return XCORR_ERR_UNSUPPORTED;
+    }
+    const int64_t wmax = window_req > 0 ? window_req : lim;
+    if (ntime <= wmax) {
+        p.window = ntime > 0 ? ntime : 1;
+        p.nwindows = ntime > 0 ? 1 : 0;
+    } else {
+        const int64_t w = window_req > 0 ? window_req : (lim >= 64 ? (lim / 64) * 64 : lim);
+        p.window = (int)w;
+        p.nwindows = (int)((ntime + w - 1) / w);
+    }
+
     int tile = acc == ACC_F32_CMAC ? 64 : (p.nin > 64 ? 128 : 64);
     // Above 192 inputs the whole-channel kernel computes at most 36/28 of the useful blocks
     // and reads every sample once, in whole rows.
@@ -166,21 +189,22 @@ int make_plan(int nstation, int npol, int nchan, int ntime, int in_fmt, int acc,
     // once per block in LDS) when their padding of the last super-row costs at most 15 %
     // more computed blocks than 128-tiles (equal at multiples of 256; the pieces run
     // 1.15-1.3x faster per block).
-    if (super_kernel_ok(p.nin, nchan, ntime, in_fmt, acc, max_abs) &&
+    if (super_kernel_ok(p.nin, nchan, p.window, in_fmt, acc, max_abs) &&
         computed_pairs_per_sample(p.nin, SUPER_TILE, acc) * 100 <= computed_pairs_per_sample(p.nin, 128, acc) * 115)
         tile = SUPER_TILE;
     if (tile_override) {
         bool ok;
         if (acc == ACC_F32_CMAC) ok = tile_override == 64;
         else if (tile_override == CHAN_TILE) ok = chan_kernel_ok(p.nin, in_fmt, acc);
-        else if (tile_override == SUPER_TILE) ok = super_kernel_ok(p.nin, nchan, ntime, in_fmt, acc, max_abs);
+        else if (tile_override == SUPER_TILE) ok = super_kernel_ok(p.nin, nchan, p.window, in_fmt, acc, max_abs);
         else ok = tile_override == 64 || tile_override == 128;
         if (!ok) {
             *err = tile_override == CHAN_TILE
                        ? "tile 256 (whole channel) needs CI8 input, the int8 or fp16 path and nin <= 256, a multiple of 8"
                    : tile_override == SUPER_TILE
-                       ? "tile 512 (super-tiles) needs CI4 input, the int8 path, nin a multiple of 256 in 512..2048 "
-                         "and ntime <= (2^31-1) / (128 max_abs^2)"
+                       ? "tile 512 (super-tiles) needs CI4 input on the int8 or fp8 path or CI8 input on the int8 "
+                         "path, nin a multiple of 16 in 272..2048, and for CI4 on the int8 path windows of at most "
+                         "(2^31-1) / (128 max_abs^2) samples"
                        : "unsupported tile size";
             return XCORR_ERR_INVALID_ARG;
         }
@@ -195,15 +219,6 @@ int make_plan(int nstation, int npol, int nchan, int ntime, int in_fmt, int acc,
         p.tiles_per_chan = p.ntile_side * (p.ntile_side + 1) / 2;
     }
 
-    const int64_t lim = window_limit(in_fmt, acc, in_fmt == IN_CF32 ? 1 : max_abs);
-    if (ntime <= lim) {
-        p.window = ntime > 0 ? ntime : 1;
-        p.nwindows = ntime > 0 ? 1 : 0;
-    } else {
-        const int64_t w = lim >= 64 ? (lim / 64) * 64 : lim;
-        p.window = (int)w;
-        p.nwindows = (int)((ntime + w - 1) / w);
-    }
     const bool wide = p.nwindows > 1;
     if (acc == ACC_I8) p.out_dtype = wide ? OUT_CI64 : OUT_CI32;
     else p.out_dtype = wide ? OUT_C128 : OUT_C64;

@@ -13,6 +13,7 @@ struct Plan {
     int in_fmt = 0, acc = 0, max_abs = 0;
     int nin = 0, tile = 0, ntile_side = 0, tiles_per_chan = 0;
     int window = 0, nwindows = 0, out_dtype = 0;
+    int window_req = 0;  // window the caller asked for (0: the longest exact one)
     int64_t nitems = 0, useful_cmacs = 0, computed_cmacs = 0;
     size_t in_bytes = 0, out_bytes = 0;
 };
@@ -23,10 +24,11 @@ int64_t window_limit(int in_fmt, int acc, int max_abs);
 // Default component bound of a sample format for an arithmetic path.
 int default_max_abs(int in_fmt, int acc);
 
-// Fill `pl`.  tile_override 0 picks the default tile.  Returns an XCORR_* code and sets
-// *err on failure.
+// Fill `pl`.  tile_override 0 picks the default tile; window_req 0 integrates in the longest
+// exact windows, a positive value in windows of that many samples (at most the exact limit).
+// Returns an XCORR_* code and sets *err on failure.
 int make_plan(int nstation, int npol, int nchan, int ntime, int in_fmt, int acc, int max_abs,
-              int tile_override, Plan *pl, std::string *err);
+              int tile_override, Plan *pl, std::string *err, int window_req = 0);
 
 // Tile value of the whole-channel kernel: one workgroup holds the triangle of up to 256
 // inputs of a channel.
@@ -42,9 +44,9 @@ constexpr int SUPER_TILE = 512;
 
 // Whether the super-tiled kernel accepts a job: CI4 samples on the int8 or fp8 path or CI8
 // samples on the int8 path, nin a multiple of 16 in 272..2048; for CI4 on the int8 path
-// also one window of its scaled operands (floor((2^31-1)/(128 m^2)) samples for samples
-// bounded by m).
-bool super_kernel_ok(int nin, int nchan, int64_t ntime, int in_fmt, int acc, int max_abs);
+// also windows within the exact limit of its scaled operands (floor((2^31-1)/(128 m^2))
+// samples for samples bounded by m).
+bool super_kernel_ok(int nin, int nchan, int64_t window, int in_fmt, int acc, int max_abs);
 
 // Exact inverse of g = by*(by+1)/2 + bx, 0 <= bx <= by.
 void tile_coords(int64_t g, int64_t *bx, int64_t *by);

@@ -11,6 +11,12 @@
 // pairs on or below the diagonal are stored (Sec. 4.4).
 //
 // Per complex MAC: re += ar*br + ai*bi, im += ai*br - ar*bi (4 FMAs, the 8 flops of Eq. 5).
+//
+// Float samples are summed in two levels: each staged block of TB samples goes into fresh
+// partial sums that are then added to the running sums.  A recursive fp32 sum of n terms
+// errs by up to about n u of the magnitude sum (u = 2^-24); two levels cut n from 2T to
+// 2 TB + T / TB.  Integer samples need no such care: below 2^24 every fp32 partial sum of
+// integers is exact (the accumulation windows keep them there).
 
 #include <hip/hip_runtime.h>
 
@@ -117,22 +123,41 @@ __device__ __forceinline__ void process_item(const XJob &p, int f, int g, int w,
         if (next) load(t_begin + (blk + 1) * TB);
         const float2 *rb = lds + cur * 2 * SIDE;
         const float2 *cb = rb + cside;
+        auto mac_block = [&](float (&sr)[RT][RT], float (&si)[RT][RT]) __attribute__((always_inline)) {
 #pragma unroll 4
-        for (int s = 0; s < TB; ++s) {
-            float2 x[RT], y[RT];
+            for (int s = 0; s < TB; ++s) {
+                float2 x[RT], y[RT];
 #pragma unroll
-            for (int a = 0; a < RT; ++a) x[a] = rb[s * TILE + ty + 16 * a];
+                for (int a = 0; a < RT; ++a) x[a] = rb[s * TILE + ty + 16 * a];
 #pragma unroll
-            for (int b = 0; b < RT; ++b) y[b] = cb[s * TILE + tx + 16 * b];
+                for (int b = 0; b < RT; ++b) y[b] = cb[s * TILE + tx + 16 * b];
+#pragma unroll
+                for (int a = 0; a < RT; ++a)
+#pragma unroll
+                    for (int b = 0; b < RT; ++b) {
+                        sr[a][b] = fmaf(x[a].x, y[b].x, sr[a][b]);
+                        sr[a][b] = fmaf(x[a].y, y[b].y, sr[a][b]);
+                        si[a][b] = fmaf(x[a].y, y[b].x, si[a][b]);
+                        si[a][b] = fmaf(-x[a].x, y[b].y, si[a][b]);
+                    }
+            }
+        };
+        if constexpr (IN == IN_CF32) {
+            float pr[RT][RT], pi[RT][RT];
+#pragma unroll
+            for (int a = 0; a < RT; ++a)
+#pragma unroll
+                for (int b = 0; b < RT; ++b) pr[a][b] = pi[a][b] = 0.f;
+            mac_block(pr, pi);
 #pragma unroll
             for (int a = 0; a < RT; ++a)
 #pragma unroll
                 for (int b = 0; b < RT; ++b) {
-                    accr[a][b] = fmaf(x[a].x, y[b].x, accr[a][b]);
-                    accr[a][b] = fmaf(x[a].y, y[b].y, accr[a][b]);
-                    acci[a][b] = fmaf(x[a].y, y[b].x, acci[a][b]);
-                    acci[a][b] = fmaf(-x[a].x, y[b].y, acci[a][b]);
+                    accr[a][b] += pr[a][b];
+                    acci[a][b] += pi[a][b];
                 }
+        } else {
+            mac_block(accr, acci);
         }
         if (next) store(cur ^ 1);
         __syncthreads();

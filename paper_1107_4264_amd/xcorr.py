@@ -67,6 +67,8 @@ def _load():
         "xcorr_set_max_abs": (c_int, [c_vp, c_int]),
         "xcorr_set_tile": (c_int, [c_vp, c_int]),
         "xcorr_get_tile": (c_int, [c_vp]),
+        "xcorr_set_window": (c_int, [c_vp, c_int]),
+        "xcorr_stream_set_window": (c_int, [c_vp, c_int]),
         "xcorr_autotune": (c_int, [c_vp, c_vp, c_vp, c_vp, c_int]),
         "xcorr_autotune_lookup": (c_int, [c_int, c_int, c_int, c_int, c_int, c_int, c_int]),
         "xcorr_autotune_save": (c_int, [ctypes.c_char_p]),
@@ -78,7 +80,8 @@ def _load():
         "xcorr_out_bytes": (c_sz, [c_vp]),
         "xcorr_out_type": (c_int, [c_vp]),
         "xcorr_last_error": (ctypes.c_char_p, []),
-        "xcorr_plan": (c_int, [c_int, c_int, c_int, c_int, c_int, c_int, c_int, c_int, ctypes.POINTER(PlanInfo)]),
+        "xcorr_plan": (c_int, [c_int, c_int, c_int, c_int, c_int, c_int, c_int, c_int, c_int,
+                               ctypes.POINTER(PlanInfo)]),
         "xcorr_window_limit": (c_i64, [c_int, c_int, c_int]),
         "xcorr_tile_coords": (c_int, [c_i64, ctypes.POINTER(c_i64), ctypes.POINTER(c_i64)]),
         "xcorr_batch_create": (c_vp, [c_int, c_vp, c_int, c_int]),
@@ -154,6 +157,10 @@ def xcorr_get_tile(h):
     return _check(_lib.xcorr_get_tile(h))
 
 
+def xcorr_set_window(h, window):
+    return _check(_lib.xcorr_set_window(h, window))
+
+
 def xcorr_autotune(h, in_ptr, out_ptr, stream_ptr, reps=3):
     return _check(_lib.xcorr_autotune(h, in_ptr, out_ptr, stream_ptr, reps))
 
@@ -194,9 +201,10 @@ def xcorr_out_type(h):
     return _check(_lib.xcorr_out_type(h))
 
 
-def xcorr_plan(nstation, npol, nchan, ntime, in_dtype, acc_dtype, max_abs=0, tile=0):
+def xcorr_plan(nstation, npol, nchan, ntime, in_dtype, acc_dtype, max_abs=0, tile=0, window=0):
     info = PlanInfo()
-    _check(_lib.xcorr_plan(nstation, npol, nchan, ntime, in_dtype, acc_dtype, max_abs, tile, ctypes.byref(info)))
+    _check(_lib.xcorr_plan(nstation, npol, nchan, ntime, in_dtype, acc_dtype, max_abs, tile, window,
+                           ctypes.byref(info)))
     return info.as_dict()
 
 
@@ -266,6 +274,10 @@ def xcorr_stream_set_max_abs(s, max_abs):
     return _check(_lib.xcorr_stream_set_max_abs(s, max_abs))
 
 
+def xcorr_stream_set_window(s, window):
+    return _check(_lib.xcorr_stream_set_window(s, window))
+
+
 def xcorr_stream_begin(s, out_ptr, stream_ptr):
     return _check(_lib.xcorr_stream_begin(s, out_ptr, stream_ptr))
 
@@ -331,13 +343,16 @@ class Correlator:
     """One planned job.  ``in_dtype`` / ``acc`` take the enumerators or the short names
     ('ci8', 'ci4', 'cf32' / 'f32', 'i8', 'f16', 'f8')."""
 
-    def __init__(self, nstation, npol, nchan, ntime, in_dtype="ci8", acc="f16", max_abs=None, tile=None):
+    def __init__(self, nstation, npol, nchan, ntime, in_dtype="ci8", acc="f16", max_abs=None, tile=None,
+                 window=None):
         self.nstation, self.npol, self.nchan, self.ntime = nstation, npol, nchan, ntime
         self.in_dtype = IN_NAMES.get(in_dtype, in_dtype)
         self.acc = ACC_NAMES.get(acc, acc)
         self.h = xcorr_create(nstation, npol, nchan, ntime, self.in_dtype, self.acc)
         if max_abs is not None:
             xcorr_set_max_abs(self.h, int(max_abs))
+        if window is not None:
+            xcorr_set_window(self.h, int(window))
         if tile is not None:
             xcorr_set_tile(self.h, int(tile))
 
@@ -446,13 +461,18 @@ class Stream:
     """Chunked integration with copy/compute overlap (Algorithm 1).  Chunks are host tensors
     (pinned for asynchronous copies); totals are a device tensor of the wide type."""
 
-    def __init__(self, nstation, npol, nchan, chunk_ntime, in_dtype="ci8", acc="i8", max_abs=None):
+    def __init__(self, nstation, npol, nchan, chunk_ntime, in_dtype="ci8", acc="i8", max_abs=None, window=None):
         self.nstation, self.npol, self.nchan, self.chunk_ntime = nstation, npol, nchan, chunk_ntime
         self.s = xcorr_stream_create(nstation, npol, nchan, chunk_ntime, IN_NAMES.get(in_dtype, in_dtype),
                                      ACC_NAMES.get(acc, acc))
         if max_abs is not None:
             xcorr_stream_set_max_abs(self.s, int(max_abs))
+        if window is not None:
+            xcorr_stream_set_window(self.s, int(window))
         self.out = None
+        # host chunks whose copies may still be in flight (released as the library does:
+        # push p releases chunk p - 2; end releases the rest once the stream is synchronised)
+        self._inflight = []
 
     def close(self):
         if self.s:
@@ -485,9 +505,18 @@ class Stream:
         if chunk.numel() * chunk.element_size() != xcorr_stream_chunk_bytes(self.s):
             raise ValueError("chunk size does not match the plan")
         xcorr_stream_push(self.s, ctypes.c_void_p(chunk.data_ptr()), _stream_ptr(stream))
+        self._inflight.append(chunk)
+        del self._inflight[:-2]
 
     def end(self, stream=None):
-        return xcorr_stream_end(self.s, _stream_ptr(stream))
+        """Finish the integration; synchronises `stream` so that every pushed chunk is
+        released (its copy has completed)."""
+        import torch
+
+        n = xcorr_stream_end(self.s, _stream_ptr(stream))
+        (stream if stream is not None else torch.cuda.current_stream()).synchronize()
+        self._inflight.clear()
+        return n
 
     def capture(self, chunks, out=None):
         """A HIP graph of a whole integration over these host chunks into `out`: each

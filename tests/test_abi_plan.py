@@ -289,3 +289,38 @@ def test_super_tile_ragged():
     assert auto(496) == 512 and auto(752) == 512 and auto(1008) == 512
     assert auto(496, X.IN_CI8) == 512 and auto(496, acc=X.ACC_F8E4M3_MMA_F32) == 512
     assert auto(272) == 128 and auto(400) == 128 and auto(784) == 128
+
+
+def test_requested_windows():
+    """xcorr_set_window / the window argument of xcorr_plan: windows of the requested length
+    (any length up to the exact limit), several windows -> wide output; longer than the
+    limit -> UNSUPPORTED; negative -> INVALID_ARG; 0 -> the longest exact window."""
+    p = X.xcorr_plan(128, 2, 4, 200, X.IN_CI8, X.ACC_I8_MMA_I32, 0, 0, 33)
+    assert p["window"] == 33 and p["nwindows"] == 7 and p["out_dtype"] == X.OUT_CI64
+    assert p["nitems"] == 4 * p["tiles_per_chan"] * 7
+    p = X.xcorr_plan(128, 2, 4, 200, X.IN_CI8, X.ACC_F16_MMA_F32, 0, 0, 200)
+    assert p["nwindows"] == 1 and p["out_dtype"] == X.OUT_C64
+    p = X.xcorr_plan(128, 2, 4, 200, X.IN_CI8, X.ACC_F16_MMA_F32, 0, 0, 0)
+    assert p["nwindows"] == 1 and p["window"] == 200
+    with pytest.raises(X.XcorrError) as e:
+        X.xcorr_plan(128, 2, 4, 2000, X.IN_CI8, X.ACC_F16_MMA_F32, 0, 0, 513)
+    assert e.value.code == X.ERR_UNSUPPORTED
+    with pytest.raises(X.XcorrError) as e:
+        X.xcorr_plan(128, 2, 4, 2000, X.IN_CI8, X.ACC_F16_MMA_F32, 0, 0, -1)
+    assert e.value.code == X.ERR_INVALID_ARG
+    # float samples: any window (fp64 sums of fp32 windows)
+    p = X.xcorr_plan(8, 2, 1, 1000, X.IN_CF32, X.ACC_F32_CMAC, 0, 0, 100)
+    assert p["nwindows"] == 10 and p["out_dtype"] == X.OUT_C128
+
+
+def test_super_tiles_with_requested_windows():
+    """4-bit samples on the int8 super-tiles carry 8x operands: an integration longer than
+    their scaled limit (262143 samples) runs on super-tiles once windows within that limit
+    are requested."""
+    lim = (2**31 - 1) // (128 * 64)
+    with pytest.raises(X.XcorrError):
+        X.xcorr_plan(256, 2, 2, lim + 1, X.IN_CI4, X.ACC_I8_MMA_I32, 0, 512)
+    p = X.xcorr_plan(256, 2, 2, lim + 1, X.IN_CI4, X.ACC_I8_MMA_I32, 0, 512, lim)
+    assert p["tile"] == 512 and p["nwindows"] == 2 and p["out_dtype"] == X.OUT_CI64
+    p = X.xcorr_plan(256, 2, 2, 10 * lim, X.IN_CI4, X.ACC_I8_MMA_I32, 0, 0, lim)
+    assert p["tile"] == 512

@@ -123,23 +123,42 @@ def test_empty_integration_gives_zeros(acc):
     c.close()
 
 
-def test_cf32_within_fp32_bound(oracle_mod):
-    """Float samples on the FP32 path: |error| <= gamma_T * sum |terms| per output value."""
-    ns, npol, F, T = 40, 2, 4, 300
-    rng = np.random.default_rng(11)
+@pytest.mark.parametrize("T", [300, 1000])
+def test_cf32_within_fp32_bound(oracle_mod, T):
+    """Float samples on the FP32 path: max |error| on the Cauchy-Schwarz scale,
+    |V_ij - oracle| / sqrt(|V_ii| |V_jj|) (autocorrelations of the two inputs' polarisations),
+    is at most 1e-6; also every value within the rounding bound of the two-level fp32 sum
+    (gamma_{2 TB + T/TB} times the magnitude sum, TB = 16 samples per block)."""
+    ns, npol, F = 40, 2, 4
+    rng = np.random.default_rng(11 + T)
     x = rng.standard_normal((T, F, ns * npol, 2)).astype(np.float32)
-    say("cf32")
+    say("cf32", T)
     got, _ = run_xeng(x, ns, npol, "cf32", "f32")
     want = oracle_mod.xcorr(x, ns, npol, fmt=oracle_mod.CF32)
-    # Both parts are sums of 2T products bounded by (|ar|+|ai|)(|br|+|bi|) per sample.
+    err = np.abs(refmath.as_complex_out(got) - refmath.as_complex_out(want))  # [F][nbl][npp]
+    # autocorrelation of every input: slot (p, p) of baseline (s, s)
+    s1, s2 = np.tril_indices(ns)
+    auto_bl = np.flatnonzero(s1 == s2)
+    autos = want[:, auto_bl][..., 0]  # [F][ns][npp] real parts
+    scale = np.zeros_like(err)
+    for p in range(npol):
+        for q in range(npol):
+            a_i = autos[:, s1, p * npol + p]
+            a_j = autos[:, s2, q * npol + q]
+            scale[:, :, p * npol + q] = np.sqrt(a_i * a_j)
+    cs = float((err / scale).max())
+    big = np.abs(refmath.as_complex_out(want)) >= 1.0
+    rel = float((err[big] / np.abs(refmath.as_complex_out(want))[big]).max())
+    say(f"cf32 T={T}: max error / sqrt(V_ii V_jj) = {cs:.3e}; max relative error where |V| >= 1 = {rel:.3e}")
+    assert cs <= 1e-6
+    # magnitude sums of both parts: (|ar|+|ai|)(|br|+|bi|) per sample
     y = np.zeros_like(x)
     y[..., 0] = np.abs(x[..., 0]) + np.abs(x[..., 1])
     mag = oracle_mod.xcorr(y, ns, npol, fmt=oracle_mod.CF32)[..., 0:1]
     u = 2.0**-24
-    gamma = (2 * T) * u / (1 - 2 * T * u)
-    err = np.abs(got.astype(np.float64) - want)
-    assert np.all(err <= gamma * mag)
-    say("cf32 max |error| / max |V|", float(err.max() / np.abs(want).max()))
+    n = 2 * 16 + (T + 15) // 16
+    gamma = n * u / (1 - n * u)
+    assert np.all(np.abs(got.astype(np.float64) - want) <= gamma * mag)
 
 
 @pytest.mark.parametrize("acc", PATHS)

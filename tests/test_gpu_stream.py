@@ -101,3 +101,53 @@ def test_stream_graph_replays(oracle_mod, acc):
     assert np.array_equal(as_exact_int(out2.cpu().numpy()), oracle_mod.xcorr(x, ns, npol))
     g.close()
     st.close()
+
+
+def _release_run(oracle_mod, delays):
+    """Pushes from a pool of three pinned buffers, each refilled with its next chunk right
+    after the push that releases it (push p releases chunk p - 2, so buffer p % 3 is free
+    once push p - 1 has returned).  Optional host delays (seeded) between the steps shift
+    the host against the copies and kernels."""
+    import time
+
+    import torch
+
+    from paper_1107_4264_amd import xcorr as X
+
+    device()
+    ns, npol, F, chunk, nchunk = 256, 2, 64, 256, 9
+    nin = ns * npol
+    x = synth.voltages_np(synth.SEED_BASE + 97, chunk * nchunk, F, nin, ("gauss", 30.0, 127))
+    want = oracle_mod.xcorr(x, ns, npol, chans=[0, F // 2, F - 1])
+    bufs = [torch.empty((chunk, F, nin, 2), dtype=torch.int8).pin_memory() for _ in range(3)]
+    src = [torch.from_numpy(np.ascontiguousarray(x[c * chunk:(c + 1) * chunk])) for c in range(nchunk)]
+    rng = np.random.default_rng(5)
+    st = X.Stream(ns, npol, F, chunk, "ci8", "i8")
+    out = st.empty_out()
+    X.xcorr_stream_begin(st.s, out.data_ptr(), torch.cuda.current_stream().cuda_stream)
+    bufs[0].copy_(src[0])
+    bufs[1].copy_(src[1])
+    for p in range(nchunk):
+        if p >= 2:
+            # chunk p - 3 (buffer p % 3) was released when push p - 1 returned
+            if delays:
+                time.sleep(float(rng.uniform(0.0, 0.004)))
+            bufs[p % 3].copy_(src[p])
+        if delays:
+            time.sleep(float(rng.uniform(0.0, 0.004)))
+        X.xcorr_stream_push(st.s, bufs[p % 3].data_ptr(), torch.cuda.current_stream().cuda_stream)
+    assert X.xcorr_stream_end(st.s, torch.cuda.current_stream().cuda_stream) == chunk * nchunk
+    torch.cuda.synchronize()
+    got = out[[0, F // 2, F - 1]].cpu().numpy()
+    assert np.array_equal(as_exact_int(got), want)
+    st.close()
+
+
+def test_stream_chunk_reuse_at_release_point(oracle_mod):
+    say("stream release point")
+    _release_run(oracle_mod, delays=False)
+
+
+def test_stream_chunk_reuse_random_delays(oracle_mod):
+    say("stream release point, random host delays")
+    _release_run(oracle_mod, delays=True)

@@ -87,25 +87,20 @@ def test_super_equals_tiles(acc):
     assert np.array_equal(a, b)
 
 
-def test_super_f8_windows():
+def test_super_f8_windows(oracle_mod):
     """fp8 super-tiles with two fp32 windows (131072 samples each at the default bound)
-    summed into fp64 totals: the totals equal, exactly, the sums of the two halves run as
-    single-window jobs (time split linearity; single windows are pinned to the oracle by
-    the tests above)."""
+    summed into fp64 totals, against the oracle (272 inputs: a full and a partial
+    super-row)."""
     from paper_1107_4264_amd import xcorr as X
 
-    ns, npol, F, T1, T2 = 256, 2, 1, 131072, 300
-    p = X.xcorr_plan(ns, npol, F, T1 + T2, X.IN_CI4, X.ACC_F8E4M3_MMA_F32, 0)
-    assert p["tile"] == 512 and p["nwindows"] == 2 and p["out_dtype"] == X.OUT_C128
-    v = synth.voltages_np(synth.SEED_BASE + 66, T1 + T2, F, ns * npol, ("uniform", -8, 7))
-    packed = synth.pack_ci4(v)
-    say("super f8 windows", T1 + T2)
-    full, ot = run_xeng(packed, ns, npol, "ci4", "f8")
+    ns, npol, F, T = 136, 2, 1, 131072 + 300
+    p = X.xcorr_plan(ns, npol, F, T, X.IN_CI4, X.ACC_F8E4M3_MMA_F32, 0, 512)
+    assert p["nwindows"] == 2 and p["out_dtype"] == X.OUT_C128
+    packed = synth.pack_ci4(synth.voltages_np(synth.SEED_BASE + 66, T, F, ns * npol, ("uniform", -8, 7)))
+    say("super f8 windows", T)
+    full, ot = run_xeng(packed, ns, npol, "ci4", "f8", tile=512)
     assert ot == X.OUT_C128
-    a, ota = run_xeng(packed[:T1], ns, npol, "ci4", "f8")
-    b, _ = run_xeng(packed[T1:], ns, npol, "ci4", "f8")
-    assert ota == X.OUT_C64
-    assert np.array_equal(as_exact_int(full), as_exact_int(a) + as_exact_int(b))
+    _check(full, oracle_mod.xcorr(packed, ns, npol, fmt=oracle_mod.CI4), "super-f8-windows")
 
 
 def test_super_stream_accumulates(oracle_mod):
@@ -180,21 +175,19 @@ def test_super_ci8_extreme_and_tiles(oracle_mod):
     assert np.array_equal(a, b)
 
 
-def test_super_ci8_windows():
-    """Two int32 windows (66572 samples each at the default bound) summed into the int64
-    totals equal, exactly, the two halves run as single-window jobs."""
+def test_super_ci8_windows(oracle_mod):
+    """Two int32 windows (66572 samples each at the default bound) of 8-bit super-tiles
+    summed into the int64 totals, against the oracle (272 inputs)."""
     from paper_1107_4264_amd import xcorr as X
 
-    ns, npol, F, T1, T2 = 256, 2, 1, 66572, 200
-    p = X.xcorr_plan(ns, npol, F, T1 + T2, X.IN_CI8, X.ACC_I8_MMA_I32, 0, 512)
+    ns, npol, F, T = 136, 2, 1, 66572 + 200
+    p = X.xcorr_plan(ns, npol, F, T, X.IN_CI8, X.ACC_I8_MMA_I32, 0, 512)
     assert p["nwindows"] == 2 and p["out_dtype"] == X.OUT_CI64
-    x = synth.voltages_np(synth.SEED_BASE + 72, T1 + T2, F, ns * npol, ("uniform", -127, 127))
-    say("super ci8 windows", T1 + T2)
+    x = synth.voltages_np(synth.SEED_BASE + 72, T, F, ns * npol, ("uniform", -127, 127))
+    say("super ci8 windows", T)
     full, ot = run_xeng(x, ns, npol, "ci8", "i8", tile=512)
     assert ot == X.OUT_CI64
-    a, _ = run_xeng(x[:T1], ns, npol, "ci8", "i8", tile=512)
-    b, _ = run_xeng(x[T1:], ns, npol, "ci8", "i8", tile=512)
-    assert np.array_equal(as_exact_int(full), as_exact_int(a) + as_exact_int(b))
+    _check(full, oracle_mod.xcorr(x, ns, npol), "super-ci8-windows")
 
 
 
