@@ -54,6 +54,7 @@ def parse():
     ap.add_argument("--only", default=None, help="time only this path (for profiling runs)")
     ap.add_argument("--tile", type=int, default=0,
                     help="kernel shape for the matrix-core paths: 0 automatic, 64/128 tiles, 256 whole channel")
+    ap.add_argument("--no-small", action="store_true", help="skip the 64-input launch-latency figures")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one device copy of 1 GiB (reference for HBM byte counters)")
     return ap.parse_args()
@@ -135,7 +136,7 @@ def main():
             "out_type": ["ci32", "ci64", "c64", "c128"][plan["out_dtype"]],
             "windows": plan["nwindows"],
             "tile": plan["tile"],
-            "launches_per_step": 1 if plan["nwindows"] == 1 else 2,
+            "launches_per_step": launches_per_step(plan),
         }
         outs[p] = out
         print(f"[bench] {p}: {ms:.4f} ms/step, {tflops:.1f} TFLOPS", file=sys.stderr, flush=True)
@@ -193,7 +194,118 @@ def main():
 
     if not args.no_cpu_baseline and not args.only:
         line["cpu_baseline"], line["parity"] = cpu_baseline(args, w, outs[head], ns, npol, F, T, seed)
+    if args.workload == "n256-ci8" and not args.only and not args.no_small:
+        for k in list(outs):
+            del outs[k]
+        del x
+        line["small_array"] = bench_small(args, dev)
     print(json.dumps(line), flush=True)
+
+
+def launches_per_step(plan):
+    """Kernel launches of one xcorr_run: the super-tiles run triangles and rectangles as two
+    launches, the other kernels one; several windows add the zero fill of the wide output."""
+    n = 2 if plan["tile"] == 512 else 1
+    return n + (1 if plan["nwindows"] > 1 else 0)
+
+
+SMALL = {
+    "name": "64 inputs (32 stations x 2 pol), 16 channels, 256 samples, ci8 uniform [-8, 7]",
+    "nstation": 32, "npol": 2, "nchan": 16, "ntime": 256, "dist": ("uniform", -8, 7), "seed_index": 0,
+    "paths": ("f32", "i8", "f16"), "graph_runs": 100,
+}
+
+
+def bench_small(args, dev):
+    """The small-array workload, where launch latency bounds the X-engine: per path the time
+    of one launch in a stream of back-to-back launches, and the time per run when 100 runs
+    are replayed from one captured HIP graph; algorithmic GB/s and TFLOPS from each.  The
+    CPU baseline leg times the oracle on all channels and compares every path's output of
+    both launch modes with it."""
+    import numpy as np
+    import torch
+
+    from paper_1107_4264_amd import synth
+    from paper_1107_4264_amd import xcorr as X
+
+    w = SMALL
+    ns, npol, F, T = w["nstation"], w["npol"], w["nchan"], w["ntime"]
+    nin = ns * npol
+    seed = synth.SEED_BASE + w["seed_index"]
+    xh = synth.voltages_np(seed, T, F, nin, w["dist"])
+    x = torch.from_numpy(xh).to(dev)
+    res = {"workload": w["name"]}
+    stream = torch.cuda.current_stream()
+    steps = max(args.steps, 100)
+    got = {}
+    for p in w["paths"]:
+        c = X.Correlator(ns, npol, F, T, "ci8", p, max_abs=8)
+        plan = X.xcorr_plan(ns, npol, F, T, X.IN_CI8, X.ACC_NAMES[p], 8, 0)
+        out = c.empty_out(dev)
+        for _ in range(args.warmup + 10):
+            c.run(x, out)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            c.run(x, out)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) / steps * 1e3
+        got[p + " stream"] = out.cpu().numpy()
+        # the same runs replayed from one captured graph
+        g = torch.cuda.CUDAGraph()
+        cs = torch.cuda.Stream()
+        cs.wait_stream(stream)
+        with torch.cuda.stream(cs):
+            c.run(x, out)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g, stream=cs):
+            for _ in range(w["graph_runs"]):
+                c.run(x, out)
+        torch.cuda.synchronize()
+        out.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        got[p + " graph"] = out.cpu().numpy()
+        reps = 5
+        e0.record(stream)
+        for _ in range(reps):
+            g.replay()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        us_graph = e0.elapsed_time(e1) / (reps * w["graph_runs"]) * 1e3
+        alg = plan["in_bytes"] + plan["out_bytes"]
+        useful = plan["useful_cmacs"]
+        res[p] = {
+            "us_per_launch": round(us, 3),
+            "us_per_run_graph": round(us_graph, 3),
+            "algorithmic_gbps": round(alg / (us * 1e-6) / 1e9, 2),
+            "algorithmic_gbps_graph": round(alg / (us_graph * 1e-6) / 1e9, 2),
+            "tflops": round(8.0 * useful / (us * 1e-6) / 1e12, 4),
+            "tflops_graph": round(8.0 * useful / (us_graph * 1e-6) / 1e12, 4),
+            "tile": plan["tile"],
+        }
+        print(f"[bench] small array {p}: {us:.2f} us per launch, {us_graph:.2f} us per run in a graph",
+              file=sys.stderr, flush=True)
+        del g
+        c.close()
+    res["algorithmic_bytes"] = alg
+    res["useful_flops"] = 8 * useful
+    if not args.no_cpu_baseline:
+        import oracle
+
+        oracle.build()
+        t0 = time.perf_counter()
+        want = oracle.xcorr(xh, ns, npol)
+        dt = time.perf_counter() - t0
+        bad = [k for k, v in got.items() if not np.array_equal(np.rint(v).astype(np.int64), want)]
+        res["cpu_baseline"] = {"value": round(8.0 * useful / dt / 1e12, 6), "unit": "TFLOPS",
+                               "cores": oracle.num_threads(), "kind": "oracle",
+                               "sample": f"all {F} channels, {dt * 1e3:.2f} ms wall"}
+        res["parity"] = ("every path, launched alone and replayed from the graph, bit-exact against the oracle"
+                         if not bad else "MISMATCH against the oracle: " + ", ".join(bad))
+    return res
 
 
 BATCH = {

@@ -169,7 +169,8 @@ int xcorr_autotune_load(const char *path);
 void xcorr_autotune_clear(void);
 
 /* Compute the visibilities of `in` (device, xcorr_in_bytes) into `out` (device,
- * xcorr_out_bytes) on `stream` (0 = the null stream). */
+ * xcorr_out_bytes) on `stream` (0 = the null stream).  The device the handle was created on
+ * must be current (XCORR_ERR_INVALID_ARG otherwise). */
 int xcorr_run(xcorr_handle_t *h, const void *in, void *out, hipStream_t stream);
 
 void xcorr_destroy(xcorr_handle_t *h);
@@ -211,7 +212,8 @@ int xcorr_batch_set_max_abs(xcorr_batch_t *b, int max_abs);
  * on `stream`: a small upload of the job table, zero fills of the outputs that sum several
  * windows, the launches of each job that the planner gives the whole-channel or the
  * super-tiled kernel (see xcorr_set_tile), and one persistent launch of the tiled kernel
- * over the work items of all other jobs.  May wait on the host for the previous run's table upload to finish. */
+ * over the work items of all other jobs.  May wait on the host for the previous run's table
+ * upload to finish.  The device the batch was created on must be current. */
 int xcorr_batch_run(xcorr_batch_t *b, const void *const *in, void *const *out, hipStream_t stream);
 
 size_t xcorr_batch_in_bytes(const xcorr_batch_t *b, int job);

@@ -33,6 +33,19 @@ int hip_fail(int e, const char *what)
     return fail(XCORR_ERR_HIP, buf);
 }
 
+// Objects are tied to the device that was current when they were created (their kernels'
+// grids, LDS limits and workspace belong to it).
+int check_device(int device)
+{
+    int cur = 0;
+    const hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return hip_fail((int)e, "hipGetDevice");
+    if (cur != device)
+        return fail(XCORR_ERR_INVALID_ARG, "object created on device " + std::to_string(device) +
+                                               " used with device " + std::to_string(cur) + " current");
+    return XCORR_OK;
+}
+
 constexpr int64_t MAX_BLOCKS_PER_LAUNCH = (1 << 24) - 8;
 
 // Global-load width a kernel may use: whole chunks of `ci` inputs when every row start is
@@ -374,6 +387,7 @@ int xcorr_run(xcorr_handle_t *h, const void *in, void *out, hipStream_t stream)
 {
     if (!h) return fail(XCORR_ERR_INVALID_ARG, "null handle");
     if (!out || (!in && h->plan.ntime > 0)) return fail(XCORR_ERR_INVALID_ARG, "null input or output");
+    if (int rc = check_device(h->device)) return rc;
     return enqueue_job(h->plan, in, out, stream);
 }
 
@@ -577,6 +591,7 @@ int xcorr_batch_run(xcorr_batch_t *b, const void *const *in, void *const *out, h
     for (int j = 0; j < njobs; ++j)
         if (!out[j] || (!in[j] && b->plans[j].ntime > 0))
             return fail(XCORR_ERR_INVALID_ARG, "null input or output of job " + std::to_string(j));
+    if (int rc = check_device(b->device)) return rc;
     hipError_t e;
     if (b->upload_pending) {
         // the pinned table is still being read by the previous run's copy
@@ -763,6 +778,7 @@ int xcorr_stream_set_window(xcorr_stream_t *s, int window)
 int xcorr_stream_begin(xcorr_stream_t *s, void *out, hipStream_t stream)
 {
     if (!s || !out) return fail(XCORR_ERR_INVALID_ARG, "null stream object or output");
+    if (int rc = check_device(s->device)) return rc;
     if (s->plan.acc == ACC_F8 && s->plan.max_abs > 16)
         return fail(XCORR_ERR_UNSUPPORTED, "fp8 e4m3 needs max_abs <= 16 (call xcorr_stream_set_max_abs)");
     Plan wide = s->plan;

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
+
 namespace xc {
 
 enum InFmt { IN_CI8 = 0, IN_CI4 = 1, IN_CF32 = 2 };
@@ -71,5 +73,23 @@ int launch_cmac_batch(const XJob *jobs_dev, const XItem *items_dev, const XQueue
 
 // Number of compute units of the current device (for persistent grids).
 int device_cus();
+
+// Raise the dynamic-LDS limit of `Kernel` to `bytes` on the current device, once per device
+// (the attribute belongs to the device that is current when it is set; one flag bit per
+// device, devices past 63 set it at every launch).
+template <auto Kernel>
+int allow_lds_on_device(int bytes)
+{
+    static std::atomic<uint64_t> done{0};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return (int)e;
+    const uint64_t bit = dev >= 0 && dev < 64 ? (uint64_t)1 << dev : 0;
+    if (bit && (done.load(std::memory_order_acquire) & bit)) return 0;
+    e = hipFuncSetAttribute((const void *)Kernel, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e != hipSuccess) return (int)e;
+    done.fetch_or(bit, std::memory_order_acq_rel);
+    return 0;
+}
 
 }  // namespace xc

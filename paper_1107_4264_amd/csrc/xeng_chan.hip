@@ -4,7 +4,7 @@
 // For such arrays one workgroup owns all the baselines of a channel (the whole lower
 // triangle of Eq. 4 at 32x32 block granularity: 8 block rows, 36 blocks), so every input
 // sample is read from HBM exactly once, as whole 512-byte rows of the [time][channel]
-// [input] layout of Sec. 5.1; splitting a row between tiles costs half the bandwidth on
+// [input] layout of Sec. 4.1; splitting a row between tiles costs half the bandwidth on
 // this memory system.  The workgroup is persistent: it walks channels (and accumulation
 // windows) blockIdx.x, blockIdx.x + gridDim.x, ... with one workgroup per compute unit.
 //
@@ -246,25 +246,11 @@ __global__ __launch_bounds__(CT, 1) void xeng_chan_kernel(XJob p)
 }
 
 
-// Dynamic LDS beyond the default limit, set once per kernel (one flag per path).
-template <int ACC>
-int allow_lds_chan()
-{
-    static int done = 0;
-    if (!done) {
-        const hipError_t e = hipFuncSetAttribute((const void *)xeng_chan_kernel<ACC>,
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize, Geom<ACC>::LDS);
-        if (e != hipSuccess) return (int)e;
-        done = 1;
-    }
-    return 0;
-}
-
 template <int ACC>
 int launch_chan_acc(const XJob &job, hipStream_t stream)
 {
     auto k = xeng_chan_kernel<ACC>;
-    if (int e = allow_lds_chan<ACC>()) return e;
+    if (int e = allow_lds_on_device<xeng_chan_kernel<ACC>>(Geom<ACC>::LDS)) return e;
     hipLaunchKernelGGL(k, dim3((unsigned)job.grid), dim3(CT), Geom<ACC>::LDS, stream, job);
     return (int)hipGetLastError();
 }

@@ -635,26 +635,12 @@ __global__ __launch_bounds__(NTHREADS, 2) void xeng_mfma_batch_kernel(const XJob
     }
 }
 
-// Kernels use more than the default 64 KiB of dynamic LDS; raise the limit once per kernel
-// (the kernel is a template argument, so every kernel has its own flag).
-template <auto Kernel>
-int allow_lds(int bytes)
-{
-    static int done = 0;
-    if (!done) {
-        const hipError_t e = hipFuncSetAttribute((const void *)Kernel, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-        if (e != hipSuccess) return (int)e;
-        done = 1;
-    }
-    return 0;
-}
-
 template <int ACC, int IN, int TILE, int MODE>
 int launch_mode(const XJob &job, hipStream_t stream)
 {
     constexpr int LDS = Tile<ACC, IN, TILE>::LDS_BYTES;
     auto k = xeng_mfma_kernel<ACC, IN, TILE, MODE>;
-    if (int e = allow_lds<xeng_mfma_kernel<ACC, IN, TILE, MODE>>(LDS)) return e;
+    if (int e = allow_lds_on_device<xeng_mfma_kernel<ACC, IN, TILE, MODE>>(LDS)) return e;
     hipLaunchKernelGGL(k, dim3((unsigned)job.grid), dim3(NTHREADS), LDS, stream, job);
     return (int)hipGetLastError();
 }
@@ -673,7 +659,7 @@ int launch_batch(const XJob *jobs, const XItem *items, const XQueues &q, unsigne
 {
     constexpr int LDS = Tile<ACC, IN, TILE>::LDS_BYTES;
     auto k = xeng_mfma_batch_kernel<ACC, IN, TILE, MODE>;
-    if (int e = allow_lds<xeng_mfma_batch_kernel<ACC, IN, TILE, MODE>>(LDS)) return e;
+    if (int e = allow_lds_on_device<xeng_mfma_batch_kernel<ACC, IN, TILE, MODE>>(LDS)) return e;
     hipLaunchKernelGGL(k, dim3(nblocks), dim3(NTHREADS), LDS, stream, jobs, items, q, counters);
     return (int)hipGetLastError();
 }

@@ -360,13 +360,7 @@ template <int ACC, int IN, int TRI>
 int launch_super_kind(XJob job, int cus, hipStream_t stream)
 {
     constexpr int LDS = SGeo<IN>::LDS;
-    static int done = 0;
-    if (!done) {
-        const hipError_t e = hipFuncSetAttribute((const void *)xeng_super_kernel<ACC, IN, TRI>,
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize, LDS);
-        if (e != hipSuccess) return (int)e;
-        done = 1;
-    }
+    if (int e = allow_lds_on_device<xeng_super_kernel<ACC, IN, TRI>>(LDS)) return e;
     const int ns = job.ntile_side;
     job.nitems = (int64_t)job.nwindows * job.nchan * (TRI ? ns : ns * (ns - 1));
     job.grid = job.nitems < cus ? job.nitems : cus;

@@ -1,7 +1,8 @@
 """Arithmetic-intensity and roofline model of the X-engine (Sec. 2.2, Sec. 4.1 / Table 1).
 
-Used by the benchmark to state algorithmic bytes, flops and bounds; no part of the compute
-path.
+The paper's tile arithmetic (checked against Table 1 by the tests) and the MI355X peaks; the
+benchmark takes its per-launch bytes and operation counts from the planner instead.  No part
+of the compute path.
 """
 
 from __future__ import annotations
