@@ -28,15 +28,33 @@ WORKLOADS = {
     "n256-ci8": {
         "name": "256 inputs (128 stations x 2 pol), 1024 channels, 1000 samples, ci8 gaussian sigma=3 clipped to +-127",
         "nstation": 128, "npol": 2, "nchan": 1024, "ntime": 1000, "in": "ci8",
-        "dist": ("gauss", 3.0, 127), "seed_index": 1, "paths": "f32,f16,i8", "head": "f16",
+        "dist": ("gauss", 3.0, 127), "seed_index": 1, "paths": "f32,f16,i8,f32m", "head": "f16",
+        # the same arithmetic on other kernel shapes: 128-tiles staged in LDS against 128-tiles
+        # whose waves load their operands through the caches (no LDS)
+        "ablation": "f16:128,f16:128:cache,i8:128,i8:128:cache,f32m:128:cache",
     },
     "n1024-ci4": {
         "name": "1024 inputs (512 stations x 2 pol), 256 channels, 4096 samples, ci4 uniform [-8, 7]",
         "nstation": 512, "npol": 2, "nchan": 256, "ntime": 4096, "in": "ci4",
-        "dist": ("uniform", -8, 7), "seed_index": 2, "paths": "i8,f8", "head": "i8",
+        "dist": ("uniform", -8, 7), "seed_index": 2, "paths": "i8,f8,f6", "head": "i8",
     },
 }
-PEAK_TFLOPS = {"f16": 2500.0, "i8": 5000.0, "f8": 5000.0, "f32": 157.3}
+PEAK_TFLOPS = {"f16": 2500.0, "i8": 5000.0, "f8": 5000.0, "f32": 157.3, "f32m": 157.3, "f6": 10100.0}
+
+
+def parse_spec(spec):
+    """Path spec acc[:tile][:cache][:vN]: arithmetic path, kernel tile (0: automatic), staging
+    through the caches instead of LDS, compile-time kernel variant."""
+    parts = spec.split(":")
+    acc, tile, staging, variant = parts[0], 0, 0, 0
+    for q in parts[1:]:
+        if q == "cache":
+            staging = 1
+        elif q.startswith("v"):
+            variant = int(q[1:])
+        else:
+            tile = int(q)
+    return acc, tile, staging, variant
 HBM_PEAK_GBPS = 8000.0
 
 
@@ -55,6 +73,7 @@ def parse():
     ap.add_argument("--tile", type=int, default=0,
                     help="kernel shape for the matrix-core paths: 0 automatic, 64/128 tiles, 256 whole channel")
     ap.add_argument("--no-small", action="store_true", help="skip the 64-input launch-latency figures")
+    ap.add_argument("--no-ablation", action="store_true", help="skip the other kernel shapes of the workload")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one device copy of 1 GiB (reference for HBM byte counters)")
     return ap.parse_args()
@@ -101,10 +120,16 @@ def main():
     results = {}
     outs = {}
     stream = torch.cuda.current_stream()
-    for p in paths:
-        tile = args.tile if p != "f32" else 0
-        c = X.Correlator(ns, npol, F, T, fmt, p, max_abs=max_abs, tile=tile)
-        plan = X.xcorr_plan(ns, npol, F, T, in_enum, X.ACC_NAMES[p], max_abs, tile)
+    specs = list(paths)
+    if not args.only and not args.no_ablation and w.get("ablation"):
+        specs += w["ablation"].split(",")
+    for p in specs:
+        acc, tile, staging, variant = parse_spec(p)
+        if tile == 0 and acc != "f32":
+            tile = args.tile
+        c = X.Correlator(ns, npol, F, T, fmt, acc, max_abs=max_abs, tile=tile or None, staging=staging or None,
+                         variant=variant or None)
+        plan = X.xcorr_plan(ns, npol, F, T, in_enum, X.ACC_NAMES[acc], max_abs, c.tile)
         out = c.empty_out(dev)
         # clocks ramp up under load: run the path untimed for a while, then the warmup steps
         t_ramp = time.perf_counter()
@@ -115,13 +140,14 @@ def main():
         for _ in range(args.warmup):
             c.run(x, out)
         torch.cuda.synchronize()
+        steps = args.steps if p in paths else max(1, min(args.steps, 20))
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        for _ in range(args.steps):
+        for _ in range(steps):
             c.run(x, out)
         e1.record(stream)
         torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / args.steps
+        ms = e0.elapsed_time(e1) / steps
         useful = plan["useful_cmacs"]
         computed = plan["computed_cmacs"]
         tflops = 8.0 * useful / (ms * 1e-3) / 1e12
@@ -130,14 +156,17 @@ def main():
             "ms_per_step": ms,
             "tflops": tflops,
             "normalised_tflops": 8.0 * computed / (ms * 1e-3) / 1e12,
-            "peak_tflops": PEAK_TFLOPS[p],
-            "frac_of_peak": tflops / PEAK_TFLOPS[p],
+            "peak_tflops": PEAK_TFLOPS[acc],
+            "frac_of_peak": tflops / PEAK_TFLOPS[acc],
             "algorithmic_gbps": alg_bytes / (ms * 1e-3) / 1e9,
             "out_type": ["ci32", "ci64", "c64", "c128"][plan["out_dtype"]],
             "windows": plan["nwindows"],
             "tile": plan["tile"],
+            "staging": "caches" if c.staging else "lds",
+            "variant": c.variant,
             "launches_per_step": launches_per_step(plan),
         }
+        c.close()
         outs[p] = out
         print(f"[bench] {p}: {ms:.4f} ms/step, {tflops:.1f} TFLOPS", file=sys.stderr, flush=True)
 
@@ -160,7 +189,8 @@ def main():
 
     head = w["head"] if w["head"] in results else paths[0]
     hr = results[head]
-    plan = X.xcorr_plan(ns, npol, F, T, in_enum, X.ACC_NAMES[head], max_abs, args.tile if head != "f32" else 0)
+    hacc = parse_spec(head)[0]
+    plan = X.xcorr_plan(ns, npol, F, T, in_enum, X.ACC_NAMES[hacc], max_abs, hr["tile"])
     line = {
         "metric": METRIC,
         "value": round(hr["tflops"], 3),
@@ -172,18 +202,18 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"f16": "f16", "i8": "i8", "f32": "f32", "f8": "fp8"}[head],
+        "dtype": {"f16": "f16", "i8": "i8", "f32": "f32", "f8": "fp8", "f32m": "f32", "f6": "fp6"}[hacc],
         "data": "synthetic",
         "config": {"workload": w["name"], "nstation": ns, "npol": npol, "nchan": F, "ntime": T,
                    "in_dtype": fmt, "max_abs": max_abs, "tile": plan["tile"],
-                   "path": f"{head} mfma" if head != "f32" else "f32 cmac"},
+                   "path": f"{head} mfma" if hacc != "f32" else "f32 cmac"},
         "roofline": {
-            "bound": "mfma" if head != "f32" else "alu",
+            "bound": "mfma" if hacc != "f32" else "alu",
             "achieved": round(hr["tflops"], 3),
-            "peak": PEAK_TFLOPS[head],
+            "peak": PEAK_TFLOPS[hacc],
             "unit": "TFLOP/s",
             "frac": round(hr["frac_of_peak"], 4),
-            "traffic": hbm_traffic(head, plan) if args.workload == "n256-ci8" else None,
+            "traffic": hbm_traffic(head, plan) if args.workload == "n256-ci8" and head == hacc else None,
         },
         "paths": {k: {kk: (round(vv, 5) if isinstance(vv, float) else vv) for kk, vv in r.items()}
                   for k, r in results.items()},

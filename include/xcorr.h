@@ -37,6 +37,14 @@
  *                             |sample| <= 16, so it accepts CI4, or CI8 after
  *                             xcorr_set_max_abs(h, m) with m <= 16; otherwise the run is
  *                             refused with XCORR_ERR_UNSUPPORTED.
+ *   XCORR_ACC_F32_MMA_F32     the plain path's FP32 arithmetic on the fp32 matrix cores
+ *                             (v_mfma_f32_32x32x2_f32), fp32 accumulation; CI8 and CI4
+ *                             samples (exact like the fp16 path), tiled kernel only.
+ *   XCORR_ACC_F6E3M2_MMA_F32  fp6 e3m2 operands on the scaled f8f6f4 matrix cores, fp32
+ *                             accumulation; e3m2 holds every integer of [-8, 8] exactly
+ *                             (Sec. 2.3's few-bit digitised data), so it accepts CI4, or
+ *                             CI8 after xcorr_set_max_abs(h, m) with m <= 8; otherwise the
+ *                             run is refused with XCORR_ERR_UNSUPPORTED.  Tiled kernel.
  *
  * Exactness and the output type.  Integer samples with |component| <= max_abs grow any
  * accumulator by at most 2*max_abs^2 per sample.  The library integrates in windows of at
@@ -82,7 +90,9 @@ typedef enum {
     XCORR_ACC_F32_CMAC = 0,
     XCORR_ACC_I8_MMA_I32 = 1,
     XCORR_ACC_F16_MMA_F32 = 2,
-    XCORR_ACC_F8E4M3_MMA_F32 = 3
+    XCORR_ACC_F8E4M3_MMA_F32 = 3,
+    XCORR_ACC_F32_MMA_F32 = 4,
+    XCORR_ACC_F6E3M2_MMA_F32 = 5
 } xcorr_acc_dtype;
 
 typedef enum {
@@ -133,11 +143,32 @@ int xcorr_set_max_abs(xcorr_handle_t *h, int max_abs);
  *        (2^31 - 1) / (128 max_abs^2) samples (its operands are the samples times 8).
  *        Same alignment fallback.
  * All shapes give bit-identical visibilities.  XCORR_ERR_INVALID_ARG for a shape the job
- * does not allow (the handle keeps its previous shape). */
+ * does not allow (the handle keeps its previous shape).  Resets the kernel variant to 0 and
+ * keeps the staging (tiles 256 / 512 need XCORR_STAGE_LDS). */
 int xcorr_set_tile(xcorr_handle_t *h, int tile);
 
 /* The kernel shape the handle runs (64, 128, 256 or 512), or an error code. */
 int xcorr_get_tile(const xcorr_handle_t *h);
+
+/* Operand staging of the tiled kernel (tiles 64 / 128): the software-managed cache of
+ * Sec. 4.4 (operands staged in LDS, the default) or the hardware-managed cache of Sec. 4.3
+ * (every wave loads its own operands from memory through the L1 and L2 caches, no LDS).
+ * The whole-channel and super-tiled kernels always stage in LDS, so XCORR_STAGE_CACHE
+ * switches such a handle to the automatic tiled shape (128, or 64 for nin <= 64).  Not for
+ * the FP32 CMAC path (XCORR_ERR_UNSUPPORTED).  Same visibilities either way. */
+typedef enum { XCORR_STAGE_LDS = 0, XCORR_STAGE_CACHE = 1 } xcorr_staging;
+int xcorr_set_staging(xcorr_handle_t *h, int staging);
+int xcorr_get_staging(const xcorr_handle_t *h);
+
+/* Compile-time variant of the kernel (the tuning parameters of Sec. 4.3 / 4.4 fixed per
+ * kernel build): whole-channel kernel (tile 256) 0..3 — bit 0 keeps one time block fewer in
+ * the LDS copy ring (int8: 3 instead of 4 blocks of 64 samples; fp16: 4 instead of 5 of
+ * 32), bit 1 swaps which of the two waves sharing a SIMD takes the five-block work list;
+ * super-tiles (tile 512) 0..1 — bit 0 uses a three-block instead of a four-block ring; the
+ * other kernels have variant 0 only.  XCORR_ERR_INVALID_ARG outside that range.  Same
+ * visibilities for every variant. */
+int xcorr_set_variant(xcorr_handle_t *h, int variant);
+int xcorr_get_variant(const xcorr_handle_t *h);
 
 /* Accumulation window (the dump interval of Sec. 2.3's wider accumulators): integrate in
  * windows of `window` samples, each summed into the wide output (ci64 / c128) when the run
@@ -148,22 +179,32 @@ int xcorr_get_tile(const xcorr_handle_t *h);
  * xcorr_set_max_abs keeps the requested window.  XCORR_ERR_INVALID_ARG for window < 0. */
 int xcorr_set_window(xcorr_handle_t *h, int window);
 
-/* Autotuner (the tile-size search of Sec. 4.2 / 6, done on the device): run every kernel
- * shape the job allows `reps` times (after one warm-up) on `in` / `out` on `stream`, timed
- * with HIP events, keep the fastest on the handle and record it in the process-wide tuning
- * cache under the job's shape (nstation, npol, nchan, ntime, formats, max_abs).  Handles
- * created or re-planned later with a cached shape start with the tuned tile.  Returns the
- * chosen tile (> 0) or an error code.  Synchronises the host with `stream`; `out` holds the
+/* Autotuner (the parameter search of Sec. 4.3 / 4.4 and 6, done on the device): run every
+ * kernel shape the job allows — tile (xcorr_set_tile) x staging (xcorr_set_staging) x
+ * kernel variant (xcorr_set_variant) — `reps` times (after one warm-up) on `in` / `out` on
+ * `stream`, timed with HIP events, keep the fastest on the handle and record it in the
+ * process-wide tuning cache under the job's class: the current device's architecture
+ * (e.g. "gfx950"), nstation, npol, formats, max_abs, requested window, and the power-of-two
+ * buckets ceil(log2(nchan)) and ceil(log2(ntime)).  Handles created or re-planned later
+ * whose job falls in a cached class start with the tuned shape.  Returns the chosen tile
+ * (> 0) or an error code.  Synchronises the host with `stream`; `out` holds the
  * visibilities of `in` afterwards (every shape gives the same bits).  reps in 1..1000. */
 int xcorr_autotune(xcorr_handle_t *h, const void *in, void *out, hipStream_t stream, int reps);
 
-/* Tile cached for a job shape (max_abs 0: the default bound), 0 if none, or an error code. */
-int xcorr_autotune_lookup(int nstation, int npol, int nchan, int ntime, xcorr_in_dtype in_dtype,
-                          xcorr_acc_dtype acc_dtype, int max_abs);
+/* The shapes the handle's last xcorr_autotune timed: returns their number; for 0 <= k <
+ * that number, fills the k-th shape and its mean time per run in microseconds (null
+ * pointers are skipped). */
+int xcorr_autotune_results(const xcorr_handle_t *h, int k, int *tile, int *staging, int *variant, double *us);
 
-/* Keep the tuning cache in a text file (one JSON object per line: the shape, "tile" and the
- * measured "us"); load merges into the cache.  Return the number of entries, or
- * XCORR_ERR_INVALID_ARG on an I/O or format error. */
+/* Kernel shape cached for a job's class on architecture `arch` (NULL: the current
+ * device's; max_abs 0: the default bound): the tile, with *staging and *variant filled
+ * (when not NULL); 0 if none; or an error code. */
+int xcorr_autotune_lookup(const char *arch, int nstation, int npol, int nchan, int ntime, xcorr_in_dtype in_dtype,
+                          xcorr_acc_dtype acc_dtype, int max_abs, int *staging, int *variant);
+
+/* Keep the tuning cache in a text file (one JSON object per line: "arch", the class,
+ * "tile", "staging", "variant" and the measured "us"); load merges into the cache.  Return
+ * the number of entries, or XCORR_ERR_INVALID_ARG on an I/O or format error. */
 int xcorr_autotune_save(const char *path);
 int xcorr_autotune_load(const char *path);
 void xcorr_autotune_clear(void);

@@ -17,7 +17,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libxcorr.so")
 OBJDIR = os.path.join(HERE, "_build")
 
-SOURCES = ["api.cpp", "plan.cpp", "tune.cpp", "xeng_mfma.hip", "xeng_chan.hip", "xeng_super.hip", "xeng_cmac.hip",
+SOURCES = ["xeng_mfma_i8.hip", "xeng_mfma_f16.hip", "xeng_mfma_f8.hip", "xeng_mfma_f32m.hip", "xeng_mfma_f6.hip",
+           "xeng_super.hip", "xeng_chan.hip", "xeng_cmac.hip", "xeng_mfma.hip", "api.cpp", "plan.cpp", "tune.cpp",
            "xeng_util.hip"]
 
 ARCH = "gfx950"

@@ -5,6 +5,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -15,6 +17,7 @@
 #include "xeng.h"
 
 using namespace xc;
+
 
 namespace {
 
@@ -76,9 +79,11 @@ XJob job_from_plan(const Plan &pl, const void *in, void *out)
     j.accumulate = pl.nwindows > 1;
     int ci = 8;
     if (pl.acc == ACC_F32_CMAC) ci = 4;
-    else if (pl.acc == ACC_F8 && pl.in_fmt == IN_CI8) ci = 4;
+    else if ((pl.acc == ACC_F8 || pl.acc == ACC_F6) && pl.in_fmt == IN_CI8) ci = 4;
     j.load_mode = load_mode_for(pl.nin, pl.in_fmt, ci);
     j.xcd_group = pl.nchan >= 8 ? 8 : 1;
+    j.staging = pl.staging;
+    j.variant = pl.variant;
     j.nitems = pl.nitems;
     const int64_t per_chan = (int64_t)pl.tiles_per_chan * pl.nwindows;
     j.grid = j.xcd_group == 8 ? 8 * ((int64_t)(pl.nchan + 7) / 8) * per_chan : pl.nitems;
@@ -113,7 +118,9 @@ int launch_job(const Plan &pl, XJob j, hipStream_t stream)
     for (int64_t b0 = 0; b0 < total; b0 += MAX_BLOCKS_PER_LAUNCH) {
         j.block0 = b0;
         j.grid = std::min<int64_t>(MAX_BLOCKS_PER_LAUNCH, total - b0);
-        const int e = pl.acc == ACC_F32_CMAC ? launch_cmac(j, pl.in_fmt, stream) : launch_mfma(j, pl.acc, pl.in_fmt, stream);
+        const int e = pl.acc == ACC_F32_CMAC ? launch_cmac(j, pl.in_fmt, stream)
+                      : pl.staging           ? launch_mfma_cache(j, pl.acc, pl.in_fmt, stream)
+                                             : launch_mfma(j, pl.acc, pl.in_fmt, stream);
         if (e) return e;
     }
     return 0;
@@ -122,8 +129,8 @@ int launch_job(const Plan &pl, XJob j, hipStream_t stream)
 // Enqueue one job: zero the output when windows are summed into it, then the tile kernels.
 int enqueue_job(const Plan &pl, const void *in, void *out, hipStream_t stream)
 {
-    if (pl.acc == ACC_F8 && pl.max_abs > 16)
-        return fail(XCORR_ERR_UNSUPPORTED, "fp8 e4m3 needs max_abs <= 16 (call xcorr_set_max_abs)");
+    if (exact_operand_bound(pl.acc) && pl.max_abs > exact_operand_bound(pl.acc))
+        return fail(XCORR_ERR_UNSUPPORTED, "fp8 e4m3 needs max_abs <= 16, fp6 e3m2 max_abs <= 8 (call xcorr_set_max_abs)");
     // The matrix-core kernels address one block of 64 samples of a channel with 32-bit
     // buffer offsets.
     if (pl.acc != ACC_F32_CMAC &&
@@ -140,20 +147,46 @@ int enqueue_job(const Plan &pl, const void *in, void *out, hipStream_t stream)
     return XCORR_OK;
 }
 
-TuneKey key_of(const Plan &p)
+// Architecture name of the current device ("gfx950"), looked up once per device;
+// "unknown" when there is no device.
+std::string current_arch()
 {
-    return TuneKey{p.nstation, p.npol, p.nchan, p.ntime, p.in_fmt, p.acc, p.max_abs};
+    static std::mutex mu;
+    static std::map<int, std::string> names;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return "unknown";
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = names.find(dev);
+    if (it != names.end()) return it->second;
+    hipDeviceProp_t prop;
+    std::string name = "unknown";
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+        name = prop.gcnArchName;
+        const size_t colon = name.find(':');
+        if (colon != std::string::npos) name.resize(colon);
+        if (name.empty()) name = "unknown";
+    }
+    names[dev] = name;
+    return name;
 }
 
-// Switch a plan to the tile the autotuner recorded for its shape, if any (and still valid).
+TuneKey key_of(const Plan &p, const std::string &arch)
+{
+    return TuneKey{arch, p.nstation, p.npol, size_class(p.nchan), size_class(p.ntime), p.in_fmt, p.acc, p.max_abs,
+                   p.window_req};
+}
+
+// Switch a plan to the kernel shape the autotuner recorded for its class on the current
+// device's architecture, if any (and still valid for the job).
 void apply_tuned(Plan &p)
 {
-    const int t = tune_lookup(key_of(p));
-    if (t == 0 || t == p.tile) return;
+    TuneVal v;
+    if (!tune_lookup(key_of(p, current_arch()), &v)) return;
+    if (v.tile == p.tile && v.staging == p.staging && v.variant == p.variant) return;
     Plan q;
     std::string err;
-    if (make_plan(p.nstation, p.npol, p.nchan, p.ntime, p.in_fmt, p.acc, p.max_abs, t, &q, &err, p.window_req) ==
-        XCORR_OK) {
+    if (make_plan(p.nstation, p.npol, p.nchan, p.ntime, p.in_fmt, p.acc, p.max_abs, v.tile, &q, &err, p.window_req,
+                  v.staging, v.variant) == XCORR_OK) {
         q.max_abs = p.max_abs;
         p = q;
     }
@@ -164,6 +197,7 @@ void apply_tuned(Plan &p)
 struct xcorr_handle {
     Plan plan;
     int device;
+    std::vector<TuneVal> tuned;  // every shape the last xcorr_autotune timed
 };
 
 extern "C" {
@@ -219,16 +253,15 @@ xcorr_handle_t *xcorr_create(int nstation, int npol, int nchan, int ntime, xcorr
 {
     Plan p;
     std::string err;
-    // An fp8 job over 8-bit samples is planned with the fp8 bound; runs are refused until
-    // the caller declares max_abs <= 16.
-    int rc = make_plan(nstation, npol, nchan, ntime, (int)in_dtype, (int)acc_dtype,
-                       (acc_dtype == XCORR_ACC_F8E4M3_MMA_F32 && in_dtype == XCORR_IN_CI8) ? 16 : 0, 0,
-                       &p, &err);
+    // An fp8 / fp6 job over 8-bit samples is planned with the operand type's bound; runs are
+    // refused until the caller declares max_abs within it.
+    const int lowcap = in_dtype == XCORR_IN_CI8 ? exact_operand_bound((int)acc_dtype) : 0;
+    int rc = make_plan(nstation, npol, nchan, ntime, (int)in_dtype, (int)acc_dtype, lowcap, 0, &p, &err);
     if (rc) {
         fail(rc, err);
         return nullptr;
     }
-    if (acc_dtype == XCORR_ACC_F8E4M3_MMA_F32 && in_dtype == XCORR_IN_CI8) p.max_abs = 128;
+    if (lowcap) p.max_abs = 128;
     apply_tuned(p);
     int dev = 0;
     hipError_t he = hipGetDevice(&dev);
@@ -254,7 +287,7 @@ int xcorr_set_max_abs(xcorr_handle_t *h, int max_abs)
     std::string err;
     const Plan &o = h->plan;
     const int rc = make_plan(o.nstation, o.npol, o.nchan, o.ntime, o.in_fmt, o.acc, max_abs, o.tile, &p, &err,
-                             o.window_req);
+                             o.window_req, o.staging, o.variant);
     if (rc) return fail(rc, err);
     apply_tuned(p);
     h->plan = p;
@@ -266,17 +299,21 @@ int xcorr_autotune(xcorr_handle_t *h, const void *in, void *out, hipStream_t str
     if (!h) return fail(XCORR_ERR_INVALID_ARG, "null handle");
     if (!out || (!in && h->plan.ntime > 0)) return fail(XCORR_ERR_INVALID_ARG, "null input or output");
     if (reps < 1 || reps > 1000) return fail(XCORR_ERR_INVALID_ARG, "reps must be in 1..1000");
+    if (int rc = check_device(h->device)) return rc;
     const Plan &o = h->plan;
+    // every kernel shape the job allows: tile x staging (tiled kernel) x compile-time variant
     std::vector<Plan> cand;
-    for (int t : {SUPER_TILE, CHAN_TILE, 128, 64}) {
-        Plan q;
-        std::string err;
-        if (make_plan(o.nstation, o.npol, o.nchan, o.ntime, o.in_fmt, o.acc, o.max_abs, t, &q, &err, o.window_req) ==
-            XCORR_OK) {
-            q.max_abs = o.max_abs;
-            cand.push_back(q);
-        }
-    }
+    for (int t : {SUPER_TILE, CHAN_TILE, 128, 64})
+        for (int st = 0; st < 2; ++st)
+            for (int v = 0; v < kernel_variants(t, o.acc); ++v) {
+                Plan q;
+                std::string err;
+                if (make_plan(o.nstation, o.npol, o.nchan, o.ntime, o.in_fmt, o.acc, o.max_abs, t, &q, &err,
+                              o.window_req, st, v) == XCORR_OK) {
+                    q.max_abs = o.max_abs;
+                    cand.push_back(q);
+                }
+            }
     if (cand.empty()) return fail(XCORR_ERR_UNSUPPORTED, "no kernel shape accepts this job");
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t he;
@@ -284,6 +321,7 @@ int xcorr_autotune(xcorr_handle_t *h, const void *in, void *out, hipStream_t str
         if (e0) (void)hipEventDestroy(e0);
         return hip_fail((int)he, "autotune events");
     }
+    std::vector<TuneVal> timed;
     int best = -1;
     double best_us = 0.0;
     int rc = XCORR_OK;
@@ -303,6 +341,7 @@ int xcorr_autotune(xcorr_handle_t *h, const void *in, void *out, hipStream_t str
             break;
         }
         const double us = 1000.0 * ms / reps;
+        timed.push_back(TuneVal{cand[c].tile, cand[c].staging, cand[c].variant, us});
         if (best < 0 || us < best_us) {
             best = (int)c;
             best_us = us;
@@ -311,19 +350,40 @@ int xcorr_autotune(xcorr_handle_t *h, const void *in, void *out, hipStream_t str
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc) return rc;
+    // leave `out` holding the chosen shape's result (bit-identical to every other shape's)
+    if ((rc = enqueue_job(cand[best], in, out, stream)) != XCORR_OK) return rc;
     h->plan = cand[best];
-    tune_record(key_of(h->plan), h->plan.tile, best_us);
+    h->tuned = timed;
+    tune_record(key_of(h->plan, current_arch()), TuneVal{h->plan.tile, h->plan.staging, h->plan.variant, best_us});
     return h->plan.tile;
 }
 
-int xcorr_autotune_lookup(int nstation, int npol, int nchan, int ntime, xcorr_in_dtype in_dtype,
-                          xcorr_acc_dtype acc_dtype, int max_abs)
+int xcorr_autotune_results(const xcorr_handle_t *h, int k, int *tile, int *staging, int *variant, double *us)
+{
+    if (!h) return fail(XCORR_ERR_INVALID_ARG, "null handle");
+    const int n = (int)h->tuned.size();
+    if (k >= 0 && k < n) {
+        const TuneVal &v = h->tuned[k];
+        if (tile) *tile = v.tile;
+        if (staging) *staging = v.staging;
+        if (variant) *variant = v.variant;
+        if (us) *us = v.us;
+    }
+    return n;
+}
+
+int xcorr_autotune_lookup(const char *arch, int nstation, int npol, int nchan, int ntime, xcorr_in_dtype in_dtype,
+                          xcorr_acc_dtype acc_dtype, int max_abs, int *staging, int *variant)
 {
     Plan p;
     std::string err;
     const int rc = make_plan(nstation, npol, nchan, ntime, (int)in_dtype, (int)acc_dtype, max_abs, 0, &p, &err);
     if (rc) return fail(rc, err);
-    return tune_lookup(key_of(p));
+    TuneVal v;
+    if (!tune_lookup(key_of(p, arch ? std::string(arch) : current_arch()), &v)) return 0;
+    if (staging) *staging = v.staging;
+    if (variant) *variant = v.variant;
+    return v.tile;
 }
 
 int xcorr_autotune_save(const char *path)
@@ -350,11 +410,52 @@ int xcorr_set_tile(xcorr_handle_t *h, int tile)
     Plan p;
     std::string err;
     const Plan &o = h->plan;
-    const int rc =
-        make_plan(o.nstation, o.npol, o.nchan, o.ntime, o.in_fmt, o.acc, o.max_abs, tile, &p, &err, o.window_req);
+    const int rc = make_plan(o.nstation, o.npol, o.nchan, o.ntime, o.in_fmt, o.acc, o.max_abs, tile, &p, &err,
+                             o.window_req, o.staging, 0);
     if (rc) return fail(rc, err);
     h->plan = p;
     return XCORR_OK;
+}
+
+int xcorr_set_staging(xcorr_handle_t *h, int staging)
+{
+    if (!h) return fail(XCORR_ERR_INVALID_ARG, "null handle");
+    Plan p;
+    std::string err;
+    const Plan &o = h->plan;
+    // keep a tiled kernel's tile; the whole-channel and super-tiled kernels always stage
+    // in LDS, so caching through L1 / L2 falls back to the automatic tile
+    const int tile = (o.tile == 64 || o.tile == 128) ? o.tile : 0;
+    const int rc = make_plan(o.nstation, o.npol, o.nchan, o.ntime, o.in_fmt, o.acc, o.max_abs, staging ? tile : 0, &p,
+                             &err, o.window_req, staging, 0);
+    if (rc) return fail(rc, err);
+    h->plan = p;
+    return XCORR_OK;
+}
+
+int xcorr_get_staging(const xcorr_handle_t *h)
+{
+    if (!h) return fail(XCORR_ERR_INVALID_ARG, "null handle");
+    return h->plan.staging;
+}
+
+int xcorr_set_variant(xcorr_handle_t *h, int variant)
+{
+    if (!h) return fail(XCORR_ERR_INVALID_ARG, "null handle");
+    Plan p;
+    std::string err;
+    const Plan &o = h->plan;
+    const int rc = make_plan(o.nstation, o.npol, o.nchan, o.ntime, o.in_fmt, o.acc, o.max_abs, o.tile, &p, &err,
+                             o.window_req, o.staging, variant);
+    if (rc) return fail(rc, err);
+    h->plan = p;
+    return XCORR_OK;
+}
+
+int xcorr_get_variant(const xcorr_handle_t *h)
+{
+    if (!h) return fail(XCORR_ERR_INVALID_ARG, "null handle");
+    return h->plan.variant;
 }
 
 int xcorr_set_window(xcorr_handle_t *h, int window)
@@ -365,12 +466,14 @@ int xcorr_set_window(xcorr_handle_t *h, int window)
     const Plan &o = h->plan;
     // an fp8 job over 8-bit samples without a declared bound plans with the fp8 bound and
     // stays refused at run time (see xcorr_create)
-    const bool undeclared = o.acc == ACC_F8 && o.in_fmt == IN_CI8 && o.max_abs > 16;
-    const int ma = undeclared ? 16 : o.max_abs;
+    const int cap = exact_operand_bound(o.acc);
+    const bool undeclared = cap && o.in_fmt == IN_CI8 && o.max_abs > cap;
+    const int ma = undeclared ? cap : o.max_abs;
     // keep a tile the caller or the autotuner chose, unless the new windows rule it out
-    int rc = make_plan(o.nstation, o.npol, o.nchan, o.ntime, o.in_fmt, o.acc, ma, o.tile, &p, &err, window);
+    int rc = make_plan(o.nstation, o.npol, o.nchan, o.ntime, o.in_fmt, o.acc, ma, o.tile, &p, &err, window, o.staging,
+                       o.variant);
     if (rc == XCORR_ERR_INVALID_ARG && window >= 0)
-        rc = make_plan(o.nstation, o.npol, o.nchan, o.ntime, o.in_fmt, o.acc, ma, 0, &p, &err, window);
+        rc = make_plan(o.nstation, o.npol, o.nchan, o.ntime, o.in_fmt, o.acc, ma, 0, &p, &err, window, o.staging, 0);
     if (rc) return fail(rc, err);
     if (undeclared) p.max_abs = o.max_abs;
     h->plan = p;
@@ -438,40 +541,55 @@ void batch_free(xcorr_batch *b)
 // upload them.  Items of one (job, channel) share a queue, so on the XCD that owns the
 // queue the tiles re-reading that channel's inputs share an L2; each queue is ordered
 // longest item first.
+// Common tile of a batch's tiled launch: 64 for the FP32 CMAC path and for arrays of at
+// most 64 inputs, 128 otherwise.
+int batch_tile(const xcorr_job *jobs, int njobs, int acc)
+{
+    int max_nin = 0;
+    for (int j = 0; j < njobs; ++j) max_nin = std::max(max_nin, jobs[j].nstation * jobs[j].npol);
+    return acc == ACC_F32_CMAC ? 64 : (max_nin > 64 ? 128 : 64);
+}
+
+// Plan job `idx` of a batch: with the batch's common tile, or with its own whole-channel or
+// super-tiled plan when the planner gives it one (*whole = 1: it runs its own persistent
+// launch).  max_abs 0: the format's default.
+int plan_batch_job(const xcorr_job &jb, int idx, int in_fmt, int acc, int max_abs, int tile, Plan *pl, char *whole)
+{
+    std::string err;
+    int ma = max_abs;
+    const int cap = in_fmt == IN_CI8 ? exact_operand_bound(acc) : 0;
+    if (cap && ma == 0) ma = cap;  // runs refused until declared
+    const int rc = make_plan(jb.nstation, jb.npol, jb.nchan, jb.ntime, in_fmt, acc, ma, tile, pl, &err);
+    if (rc) return fail(rc, "job " + std::to_string(idx) + ": " + err);
+    if (cap && max_abs == 0) pl->max_abs = 128;
+    *whole = 0;
+    Plan wp;
+    if (acc != ACC_F32_CMAC && make_plan(jb.nstation, jb.npol, jb.nchan, jb.ntime, in_fmt, acc, ma, 0, &wp, &err) == XCORR_OK &&
+        (wp.tile == CHAN_TILE || wp.tile == SUPER_TILE)) {
+        wp.max_abs = pl->max_abs;
+        *pl = wp;
+        *whole = 1;
+    }
+    if (acc != ACC_F32_CMAC && 64.0 * (double)jb.nchan * pl->nin * (double)in_sample_bytes(in_fmt) >= 4294901760.0)
+        return fail(XCORR_ERR_RANGE, "job " + std::to_string(idx) + ": nchan * nin too large");
+    return XCORR_OK;
+}
+
+// Plan every job with a common tile and load mode, build the queues of work items and
+// upload them.  Items of one (job, channel) share a queue, so on the XCD that owns the
+// queue the tiles re-reading that channel's inputs share an L2; each queue is ordered
+// longest item first.
 int batch_plan(xcorr_batch *b, int max_abs)
 {
     const int njobs = (int)b->jobs.size();
-    int max_nin = 0;
-    for (const xcorr_job &j : b->jobs) max_nin = std::max(max_nin, j.nstation * j.npol);
-    const int tile = b->acc == ACC_F32_CMAC ? 64 : (max_nin > 64 ? 128 : 64);
+    const int tile = batch_tile(b->jobs.data(), njobs, b->acc);
     std::vector<Plan> plans(njobs);
     std::vector<char> whole(njobs, 0);
-    std::string err;
-    int ci = b->acc == ACC_F32_CMAC ? 4 : ((b->acc == ACC_F8 && b->in_fmt == IN_CI8) ? 4 : 8);
+    int ci = b->acc == ACC_F32_CMAC ? 4 : ((exact_operand_bound(b->acc) && b->in_fmt == IN_CI8) ? 4 : 8);
     int mode = LOAD_VEC;
     for (int j = 0; j < njobs; ++j) {
-        const xcorr_job &jb = b->jobs[j];
-        int ma = max_abs;
-        if (b->acc == ACC_F8 && b->in_fmt == IN_CI8 && ma == 0) ma = 16;  // runs refused until declared
-        const int rc = make_plan(jb.nstation, jb.npol, jb.nchan, jb.ntime, b->in_fmt, b->acc, ma, tile, &plans[j], &err);
-        if (rc) return fail(rc, "job " + std::to_string(j) + ": " + err);
-        if (b->acc == ACC_F8 && b->in_fmt == IN_CI8 && max_abs == 0) plans[j].max_abs = 128;
-        // jobs the planner gives the whole-channel or the super-tiled kernel run it (their
-        // own persistent launches); the others share the persistent launch of the tiled
-        // kernel
-        Plan wp;
-        if (b->acc != ACC_F32_CMAC &&
-            make_plan(jb.nstation, jb.npol, jb.nchan, jb.ntime, b->in_fmt, b->acc, ma, 0, &wp, &err) == XCORR_OK &&
-            (wp.tile == CHAN_TILE || wp.tile == SUPER_TILE)) {
-            wp.max_abs = plans[j].max_abs;
-            plans[j] = wp;
-            whole[j] = 1;
-        } else {
-            mode = std::max(mode, load_mode_for(plans[j].nin, b->in_fmt, ci));
-        }
-        if (b->acc != ACC_F32_CMAC &&
-            64.0 * (double)jb.nchan * plans[j].nin * (double)in_sample_bytes(b->in_fmt) >= 4294901760.0)
-            return fail(XCORR_ERR_RANGE, "job " + std::to_string(j) + ": nchan * nin too large");
+        if (int rc = plan_batch_job(b->jobs[j], j, b->in_fmt, b->acc, max_abs, tile, &plans[j], &whole[j])) return rc;
+        if (!whole[j]) mode = std::max(mode, load_mode_for(plans[j].nin, b->in_fmt, ci));
     }
     // Work items in groups of one (job, channel, window): the tiles of a group read the same
     // input rows, so they stay adjacent in their queue (taken at about the same time by
@@ -586,8 +704,9 @@ int xcorr_batch_run(xcorr_batch_t *b, const void *const *in, void *const *out, h
 {
     if (!b || !in || !out) return fail(XCORR_ERR_INVALID_ARG, "null batch or pointer array");
     const int njobs = (int)b->jobs.size();
-    if (b->acc == ACC_F8 && b->in_fmt == IN_CI8 && b->plans[0].max_abs > 16)
-        return fail(XCORR_ERR_UNSUPPORTED, "fp8 e4m3 needs max_abs <= 16 (call xcorr_batch_set_max_abs)");
+    if (exact_operand_bound(b->acc) && b->plans[0].max_abs > exact_operand_bound(b->acc))
+        return fail(XCORR_ERR_UNSUPPORTED,
+                    "fp8 e4m3 needs max_abs <= 16, fp6 e3m2 max_abs <= 8 (call xcorr_batch_set_max_abs)");
     for (int j = 0; j < njobs; ++j)
         if (!out[j] || (!in[j] && b->plans[j].ntime > 0))
             return fail(XCORR_ERR_INVALID_ARG, "null input or output of job " + std::to_string(j));
@@ -709,15 +828,14 @@ xcorr_stream_t *xcorr_stream_create(int nstation, int npol, int nchan, int chunk
         return nullptr;
     }
     std::string err;
-    const bool f8ci8 = acc_dtype == XCORR_ACC_F8E4M3_MMA_F32 && in_dtype == XCORR_IN_CI8;
-    int rc = make_plan(nstation, npol, nchan, chunk_ntime, (int)in_dtype, (int)acc_dtype, f8ci8 ? 16 : 0, 0,
-                       &s->plan, &err);
+    const int lowcap = in_dtype == XCORR_IN_CI8 ? exact_operand_bound((int)acc_dtype) : 0;
+    int rc = make_plan(nstation, npol, nchan, chunk_ntime, (int)in_dtype, (int)acc_dtype, lowcap, 0, &s->plan, &err);
     if (rc) {
         fail(rc, err);
         delete s;
         return nullptr;
     }
-    if (f8ci8) s->plan.max_abs = 128;
+    if (lowcap) s->plan.max_abs = 128;
     if (s->plan.acc != ACC_F32_CMAC &&
         64.0 * (double)nchan * s->plan.nin * (double)in_sample_bytes(s->plan.in_fmt) >= 4294901760.0) {
         fail(XCORR_ERR_RANGE, "nchan * nin too large: 64 samples of all channels must span < 4 GiB");
@@ -766,8 +884,9 @@ int xcorr_stream_set_window(xcorr_stream_t *s, int window)
     Plan p;
     std::string err;
     const Plan &o = s->plan;
-    const bool undeclared = o.acc == ACC_F8 && o.in_fmt == IN_CI8 && o.max_abs > 16;
-    const int ma = undeclared ? 16 : o.max_abs;
+    const int cap = exact_operand_bound(o.acc);
+    const bool undeclared = cap && o.in_fmt == IN_CI8 && o.max_abs > cap;
+    const int ma = undeclared ? cap : o.max_abs;
     const int rc = make_plan(o.nstation, o.npol, o.nchan, o.ntime, o.in_fmt, o.acc, ma, 0, &p, &err, window);
     if (rc) return fail(rc, err);
     if (undeclared) p.max_abs = o.max_abs;
@@ -779,8 +898,9 @@ int xcorr_stream_begin(xcorr_stream_t *s, void *out, hipStream_t stream)
 {
     if (!s || !out) return fail(XCORR_ERR_INVALID_ARG, "null stream object or output");
     if (int rc = check_device(s->device)) return rc;
-    if (s->plan.acc == ACC_F8 && s->plan.max_abs > 16)
-        return fail(XCORR_ERR_UNSUPPORTED, "fp8 e4m3 needs max_abs <= 16 (call xcorr_stream_set_max_abs)");
+    if (exact_operand_bound(s->plan.acc) && s->plan.max_abs > exact_operand_bound(s->plan.acc))
+        return fail(XCORR_ERR_UNSUPPORTED,
+                    "fp8 e4m3 needs max_abs <= 16, fp6 e3m2 max_abs <= 8 (call xcorr_stream_set_max_abs)");
     Plan wide = s->plan;
     wide.out_dtype = wide_type(wide.acc);
     wide.out_bytes = s->plan.out_bytes / out_value_bytes(s->plan.out_dtype) * out_value_bytes(wide.out_dtype);

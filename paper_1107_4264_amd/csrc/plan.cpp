@@ -46,7 +46,7 @@ static int max_abs_cap(int in_fmt, int acc)
 // One sample adds at most |ar*br| + |ai*bi| <= 2*m^2 to a real or imaginary sum.
 int64_t window_limit(int in_fmt, int acc, int max_abs)
 {
-    if (in_fmt < IN_CI8 || in_fmt > IN_CF32 || acc < ACC_F32_CMAC || acc > ACC_F8) return -1;
+    if (in_fmt < IN_CI8 || in_fmt > IN_CF32 || acc < ACC_F32_CMAC || acc > ACC_LAST) return -1;
     if (in_fmt == IN_CF32) return acc == ACC_F32_CMAC ? INT64_MAX : -1;
     if (max_abs < 1 || max_abs > max_abs_cap(in_fmt, acc)) return -1;
     const int64_t per = 2 * (int64_t)max_abs * max_abs;
@@ -115,8 +115,16 @@ int64_t computed_pairs_per_sample(int nin, int tile, int acc)
     return total;
 }
 
+int kernel_variants(int tile, int acc)
+{
+    if (acc == ACC_F32_CMAC) return 1;
+    if (tile == CHAN_TILE) return 4;
+    if (tile == SUPER_TILE) return 2;
+    return 1;
+}
+
 int make_plan(int nstation, int npol, int nchan, int ntime, int in_fmt, int acc, int max_abs,
-              int tile_override, Plan *pl, std::string *err, int window_req)
+              int tile_override, Plan *pl, std::string *err, int window_req, int staging, int variant)
 {
     if (!pl) {
         *err = "null plan";
@@ -126,7 +134,7 @@ int make_plan(int nstation, int npol, int nchan, int ntime, int in_fmt, int acc,
         *err = "need nstation >= 1, npol in {1, 2}, nchan >= 1, ntime >= 0";
         return XCORR_ERR_INVALID_ARG;
     }
-    if (in_fmt < IN_CI8 || in_fmt > IN_CF32 || acc < ACC_F32_CMAC || acc > ACC_F8) {
+    if (in_fmt < IN_CI8 || in_fmt > IN_CF32 || acc < ACC_F32_CMAC || acc > ACC_LAST) {
         *err = "unknown input format or arithmetic path";
         return XCORR_ERR_INVALID_ARG;
     }
@@ -137,6 +145,14 @@ int make_plan(int nstation, int npol, int nchan, int ntime, int in_fmt, int acc,
     if (window_req < 0) {
         *err = "window must be >= 0 (0: the longest exact window)";
         return XCORR_ERR_INVALID_ARG;
+    }
+    if (staging != 0 && staging != 1) {
+        *err = "staging must be 0 (LDS) or 1 (caches)";
+        return XCORR_ERR_INVALID_ARG;
+    }
+    if (staging == 1 && acc == ACC_F32_CMAC) {
+        *err = "the FP32 CMAC kernel always stages its operands in LDS";
+        return XCORR_ERR_UNSUPPORTED;
     }
     const int64_t nin64 = (int64_t)nstation * npol;
     if (nin64 > 65536) {
@@ -152,6 +168,10 @@ int make_plan(int nstation, int npol, int nchan, int ntime, int in_fmt, int acc,
         *err = "fp8 e4m3 is exact only for |sample| <= 16: use CI4 or declare max_abs <= 16";
         return XCORR_ERR_UNSUPPORTED;
     }
+    if (acc == ACC_F6 && max_abs > 8) {
+        *err = "fp6 e3m2 is exact only for |sample| <= 8: use CI4 or declare max_abs <= 8";
+        return XCORR_ERR_UNSUPPORTED;
+    }
     Plan p;
     p.nstation = nstation;
     p.npol = npol;
@@ -161,6 +181,7 @@ int make_plan(int nstation, int npol, int nchan, int ntime, int in_fmt, int acc,
     p.acc = acc;
     p.max_abs = in_fmt == IN_CF32 ? 0 : max_abs;
     p.window_req = window_req;
+    p.staging = staging;
     p.nin = (int)nin64;
 
     // Accumulation windows (Sec. 2.3: accumulators wider than the data): the longest exact
@@ -183,23 +204,26 @@ int make_plan(int nstation, int npol, int nchan, int ntime, int in_fmt, int acc,
     int tile = acc == ACC_F32_CMAC ? 64 : (p.nin > 64 ? 128 : 64);
     // Above 192 inputs the whole-channel kernel computes at most 36/28 of the useful blocks
     // and reads every sample once, in whole rows.
-    if (chan_kernel_ok(p.nin, in_fmt, acc) && p.nin > 192) tile = CHAN_TILE;
+    if (chan_kernel_ok(p.nin, in_fmt, acc) && p.nin > 192 && !staging) tile = CHAN_TILE;
     // Above 256 inputs of 4-bit samples on the int8 / fp8 paths and of 8-bit samples on the
     // int8 path, super-tiles (whole 256-input pieces per workgroup, operands widened or moved
     // once per block in LDS) when their padding of the last super-row costs at most 15 %
     // more computed blocks than 128-tiles (equal at multiples of 256; the pieces run
     // 1.15-1.3x faster per block).
-    if (super_kernel_ok(p.nin, nchan, p.window, in_fmt, acc, max_abs) &&
+    if (!staging && super_kernel_ok(p.nin, nchan, p.window, in_fmt, acc, max_abs) &&
         computed_pairs_per_sample(p.nin, SUPER_TILE, acc) * 100 <= computed_pairs_per_sample(p.nin, 128, acc) * 115)
         tile = SUPER_TILE;
     if (tile_override) {
         bool ok;
         if (acc == ACC_F32_CMAC) ok = tile_override == 64;
-        else if (tile_override == CHAN_TILE) ok = chan_kernel_ok(p.nin, in_fmt, acc);
-        else if (tile_override == SUPER_TILE) ok = super_kernel_ok(p.nin, nchan, p.window, in_fmt, acc, max_abs);
+        else if (tile_override == CHAN_TILE) ok = !staging && chan_kernel_ok(p.nin, in_fmt, acc);
+        else if (tile_override == SUPER_TILE)
+            ok = !staging && super_kernel_ok(p.nin, nchan, p.window, in_fmt, acc, max_abs);
         else ok = tile_override == 64 || tile_override == 128;
         if (!ok) {
-            *err = tile_override == CHAN_TILE
+            *err = staging && (tile_override == CHAN_TILE || tile_override == SUPER_TILE)
+                       ? "staging through the caches runs the tiled kernel: tile 64 or 128"
+                   : tile_override == CHAN_TILE
                        ? "tile 256 (whole channel) needs CI8 input, the int8 or fp16 path and nin <= 256, a multiple of 8"
                    : tile_override == SUPER_TILE
                        ? "tile 512 (super-tiles) needs CI4 input on the int8 or fp8 path or CI8 input on the int8 "
@@ -211,6 +235,11 @@ int make_plan(int nstation, int npol, int nchan, int ntime, int in_fmt, int acc,
         tile = tile_override;
     }
     p.tile = tile;
+    if (variant < 0 || variant >= kernel_variants(tile, acc)) {
+        *err = "kernel variant out of range for the kernel shape (whole channel 0..3, super-tiles 0..1, others 0)";
+        return XCORR_ERR_INVALID_ARG;
+    }
+    p.variant = variant;
     if (tile == SUPER_TILE) {
         p.ntile_side = (p.nin + 255) / 256;                // super-rows
         p.tiles_per_chan = p.ntile_side * p.ntile_side;    // triangles + rectangles

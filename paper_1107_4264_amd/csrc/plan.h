@@ -14,6 +14,8 @@ struct Plan {
     int nin = 0, tile = 0, ntile_side = 0, tiles_per_chan = 0;
     int window = 0, nwindows = 0, out_dtype = 0;
     int window_req = 0;  // window the caller asked for (0: the longest exact one)
+    int staging = 0;     // 0: operands staged in LDS; 1: loaded per wave through the caches
+    int variant = 0;     // compile-time variant of the whole-channel (0..3) / super-tiled (0..1) kernel
     int64_t nitems = 0, useful_cmacs = 0, computed_cmacs = 0;
     size_t in_bytes = 0, out_bytes = 0;
 };
@@ -25,10 +27,16 @@ int64_t window_limit(int in_fmt, int acc, int max_abs);
 int default_max_abs(int in_fmt, int acc);
 
 // Fill `pl`.  tile_override 0 picks the default tile; window_req 0 integrates in the longest
-// exact windows, a positive value in windows of that many samples (at most the exact limit).
+// exact windows, a positive value in windows of that many samples (at most the exact limit);
+// staging 1 runs the tiled kernel without its LDS stage (tiles 64 / 128, matrix-core paths).
 // Returns an XCORR_* code and sets *err on failure.
 int make_plan(int nstation, int npol, int nchan, int ntime, int in_fmt, int acc, int max_abs,
-              int tile_override, Plan *pl, std::string *err, int window_req = 0);
+              int tile_override, Plan *pl, std::string *err, int window_req = 0, int staging = 0,
+              int variant = 0);
+
+// Number of compile-time variants of the kernel a tile value selects (1 for the tiled and
+// FP32 CMAC kernels).
+int kernel_variants(int tile, int acc);
 
 // Tile value of the whole-channel kernel: one workgroup holds the triangle of up to 256
 // inputs of a channel.

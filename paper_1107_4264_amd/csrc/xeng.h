@@ -9,7 +9,15 @@
 namespace xc {
 
 enum InFmt { IN_CI8 = 0, IN_CI4 = 1, IN_CF32 = 2 };
-enum AccPath { ACC_F32_CMAC = 0, ACC_I8 = 1, ACC_F16 = 2, ACC_F8 = 3 };
+// ACC_F32M: fp32 matrix cores (v_mfma_f32_32x32x2_f32), the plain path's arithmetic on the
+// matrix cores.  ACC_F6: fp6 e3m2 operands on the scaled f8f6f4 matrix cores.
+enum AccPath { ACC_F32_CMAC = 0, ACC_I8 = 1, ACC_F16 = 2, ACC_F8 = 3, ACC_F32M = 4, ACC_F6 = 5 };
+constexpr int ACC_LAST = ACC_F6;
+
+// Largest |sample component| a low-precision operand type holds exactly: fp8 e4m3 every
+// integer of [-16, 16], fp6 e3m2 every integer of [-8, 8]; 0 for the other paths (no limit
+// below the sample format's).
+constexpr int exact_operand_bound(int acc) { return acc == ACC_F8 ? 16 : (acc == ACC_F6 ? 8 : 0); }
 enum OutFmt { OUT_CI32 = 0, OUT_CI64 = 1, OUT_C64 = 2, OUT_C128 = 3 };
 
 // Global-load width the staging code may use for a job (fixed per job by nin alignment).
@@ -31,6 +39,8 @@ struct XJob {
     int accumulate;       // 1: add each window into the (pre-zeroed) wide output
     int load_mode;        // LoadMode
     int xcd_group;        // 8: keep all tiles of a channel on one XCD; 1: plain order
+    int staging;          // 0: operands staged in LDS; 1: loaded per wave through the caches
+    int variant;          // compile-time variant of the whole-channel / super-tiled kernel
     int64_t nitems;       // nchan * tiles_per_chan * nwindows
     int64_t grid;         // blocks in this launch
     int64_t block0;       // item number of block 0 (launches are split below 2^24 blocks)
@@ -46,6 +56,8 @@ struct XItem {
 
 // Launchers (return a hipError_t as int).
 int launch_mfma(const XJob &job, int acc, int in_fmt, hipStream_t stream);
+// The tiled kernel without the LDS stage (operands loaded per wave through the caches).
+int launch_mfma_cache(const XJob &job, int acc, int in_fmt, hipStream_t stream);
 int launch_cmac(const XJob &job, int in_fmt, hipStream_t stream);
 int launch_zero(void *ptr, size_t bytes, hipStream_t stream);
 // Whole-channel kernel (tile 256): persistent, job.grid workgroups of 512 threads walk the
@@ -65,11 +77,52 @@ struct XQueues {
     int64_t end[NQUEUE];
 };
 
+// Work list generated on the device instead of uploaded (for a job table in a fixed
+// workspace): queue q holds, job after job in table order, the channels f of job j
+// with (f + j) % NQUEUE == q, each as tiles_per_chan * nwindows items (window-major, the
+// tiles of one (channel, window) adjacent).  qend[q * maxj + j] counts the items of queue q
+// in jobs 0..j; qend[q * maxj + njobs - 1] is the queue's length.
+struct XGenQueues {
+    const int64_t *qend;
+    int njobs;
+    int maxj;
+};
+
+// Item `it` of queue q of a generated work list; false past the end of the queue.
+__device__ __forceinline__ bool gen_item(const XJob *jobs, const XGenQueues &g, int q, int64_t it, XItem &item)
+{
+    const int64_t *e = g.qend + (int64_t)q * g.maxj;
+    if (g.njobs <= 0 || it >= e[g.njobs - 1]) return false;
+    int lo = 0, hi = g.njobs - 1;  // first job whose cumulative count exceeds it
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (e[mid] > it) hi = mid;
+        else lo = mid + 1;
+    }
+    const XJob &jb = jobs[lo];
+    const int64_t local = it - (lo > 0 ? e[lo - 1] : 0);
+    const int64_t per_chan = (int64_t)jb.tiles_per_chan * jb.nwindows;
+    const int64_t k = local / per_chan;
+    const int64_t r = local - k * per_chan;
+    const int f0 = ((q - lo) % NQUEUE + NQUEUE) % NQUEUE;
+    item.job = lo;
+    item.chan = (int)(f0 + (int64_t)NQUEUE * k);
+    item.window = (int)(r / jb.tiles_per_chan);
+    item.tile = (int)(r - (int64_t)item.window * jb.tiles_per_chan);
+    return true;
+}
+
 int launch_mfma_batch(const XJob *jobs_dev, const XItem *items_dev, const XQueues &queues,
                       unsigned int *counters_dev, int acc, int in_fmt, int tile, int load_mode, int nblocks,
                       hipStream_t stream);
 int launch_cmac_batch(const XJob *jobs_dev, const XItem *items_dev, const XQueues &queues,
                       unsigned int *counters_dev, int in_fmt, int nblocks, hipStream_t stream);
+// The same persistent launches over a generated work list (counters zeroed by the caller).
+int launch_mfma_batch_gen(const XJob *jobs_dev, const XGenQueues &g, unsigned int *counters_dev, int acc,
+                          int in_fmt, int tile, int load_mode, int nblocks, hipStream_t stream);
+int launch_cmac_batch_gen(const XJob *jobs_dev, const XGenQueues &g, unsigned int *counters_dev, int in_fmt,
+                          int nblocks, hipStream_t stream);
+
 
 // Number of compute units of the current device (for persistent grids).
 int device_cus();

@@ -32,11 +32,11 @@
 namespace xc {
 namespace {
 
-template <int ACC, int W>
+template <int ACC, int W, int V>
 __device__ __forceinline__ void run_wave(const XJob &p, int lane)
 {
     using O = COp<ACC>;
-    using G = Geom<ACC>;
+    using G = Geom<ACC, V>;
     constexpr int TB = G::TB, RING = G::RING, DPW = G::DPW;
     constexpr int NKS = TB / O::KS;
     const uint64_t row_stride = (uint64_t)p.nchan * p.nin * 2;
@@ -224,35 +224,49 @@ __device__ __forceinline__ void run_wave(const XJob &p, int lane)
     wait_vm<0>();
 }
 
-template <int ACC>
+// Variant V: bit 0 one ring slot fewer (Geom), bit 1 the other assignment of the work lists
+// to the older and younger wave of each SIMD.
+template <int ACC, int V>
 __global__ __launch_bounds__(CT, 1) void xeng_chan_kernel(XJob p)
 {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    // Waves w and w + 4 share a SIMD and the older one (w) wins its issue conflicts.  The
-    // fp16 path gives it the five-block list and the conversion; the int8 path runs faster
-    // with the four-block squares on the older waves.
-    constexpr int X = ACC == ACC_I8 ? 4 : 0;
+    // Waves w and w + 4 share a SIMD and the older one (w) wins its issue conflicts.  By
+    // default the fp16 path gives it the five-block list and the conversion; the int8 path
+    // runs faster with the four-block squares on the older waves.
+    constexpr int X = (ACC == ACC_I8 ? 4 : 0) ^ ((V & 2) ? 4 : 0);
     switch (wave) {
-    case 0: run_wave<ACC, 0 ^ X>(p, lane); break;
-    case 1: run_wave<ACC, 1 ^ X>(p, lane); break;
-    case 2: run_wave<ACC, 2 ^ X>(p, lane); break;
-    case 3: run_wave<ACC, 3 ^ X>(p, lane); break;
-    case 4: run_wave<ACC, 4 ^ X>(p, lane); break;
-    case 5: run_wave<ACC, 5 ^ X>(p, lane); break;
-    case 6: run_wave<ACC, 6 ^ X>(p, lane); break;
-    default: run_wave<ACC, 7 ^ X>(p, lane); break;
+    case 0: run_wave<ACC, 0 ^ X, V>(p, lane); break;
+    case 1: run_wave<ACC, 1 ^ X, V>(p, lane); break;
+    case 2: run_wave<ACC, 2 ^ X, V>(p, lane); break;
+    case 3: run_wave<ACC, 3 ^ X, V>(p, lane); break;
+    case 4: run_wave<ACC, 4 ^ X, V>(p, lane); break;
+    case 5: run_wave<ACC, 5 ^ X, V>(p, lane); break;
+    case 6: run_wave<ACC, 6 ^ X, V>(p, lane); break;
+    default: run_wave<ACC, 7 ^ X, V>(p, lane); break;
     }
 }
 
 
+template <int ACC, int V>
+int launch_chan_var(const XJob &job, hipStream_t stream)
+{
+    constexpr int LDS = Geom<ACC, V>::LDS;
+    if (int e = allow_lds_on_device<xeng_chan_kernel<ACC, V>>(LDS)) return e;
+    hipLaunchKernelGGL((xeng_chan_kernel<ACC, V>), dim3((unsigned)job.grid), dim3(CT), LDS, stream, job);
+    return (int)hipGetLastError();
+}
+
 template <int ACC>
 int launch_chan_acc(const XJob &job, hipStream_t stream)
 {
-    auto k = xeng_chan_kernel<ACC>;
-    if (int e = allow_lds_on_device<xeng_chan_kernel<ACC>>(Geom<ACC>::LDS)) return e;
-    hipLaunchKernelGGL(k, dim3((unsigned)job.grid), dim3(CT), Geom<ACC>::LDS, stream, job);
-    return (int)hipGetLastError();
+    switch (job.variant) {
+    case 0: return launch_chan_var<ACC, 0>(job, stream);
+    case 1: return launch_chan_var<ACC, 1>(job, stream);
+    case 2: return launch_chan_var<ACC, 2>(job, stream);
+    case 3: return launch_chan_var<ACC, 3>(job, stream);
+    default: return (int)hipErrorInvalidValue;
+    }
 }
 
 }  // namespace

@@ -38,9 +38,10 @@ struct ChanCfg<ACC_F16> {
     static constexpr int TB = 32, RING = 5;
     static constexpr bool STAGE = true;
 };
-template <int ACC>
+// Variant V (chosen by the autotuner): bit 0 keeps one block fewer in the LDS ring.
+template <int ACC, int V = 0>
 struct Geom {
-    static constexpr int TB = ChanCfg<ACC>::TB, RING = ChanCfg<ACC>::RING;
+    static constexpr int TB = ChanCfg<ACC>::TB, RING = ChanCfg<ACC>::RING - (V & 1);
     static constexpr bool STAGE = ChanCfg<ACC>::STAGE;
     static constexpr int BLK = TB * CROW;                   // raw bytes per block
     static constexpr int DPW = TB / 2 / (CT / 64);          // copies per wave per block

@@ -238,6 +238,27 @@ __global__ __launch_bounds__(NTHREADS) void xeng_cmac_batch_kernel(const XJob *j
     }
 }
 
+template <int IN>
+__global__ __launch_bounds__(NTHREADS) void xeng_cmac_batch_gen_kernel(const XJob *jobs, XGenQueues gq,
+                                                                       unsigned int *counters)
+{
+    __shared__ __attribute__((aligned(16))) float2 lds[2 * 2 * TB * TILE];
+    __shared__ int64_t next;
+    const int q0 = blockIdx.x % NQUEUE;
+    for (int qi = 0; qi < NQUEUE; ++qi) {
+        const int qq = (q0 + qi) % NQUEUE;
+        for (;;) {
+            if (threadIdx.x == 0) next = (int64_t)atomicAdd(&counters[qq * COUNTER_STRIDE], 1u);
+            __syncthreads();
+            const int64_t it = next;
+            __syncthreads();
+            XItem item;
+            if (!gen_item(jobs, gq, qq, it, item)) break;
+            process_item<IN>(jobs[item.job], item.chan, item.tile, item.window, lds);
+        }
+    }
+}
+
 }  // namespace
 
 int launch_cmac(const XJob &job, int in_fmt, hipStream_t stream)
@@ -262,6 +283,20 @@ int launch_cmac_batch(const XJob *jobs_dev, const XItem *items_dev, const XQueue
     case IN_CI8: hipLaunchKernelGGL(xeng_cmac_batch_kernel<IN_CI8>, grid, block, 0, stream, jobs_dev, items_dev, queues, counters_dev); break;
     case IN_CI4: hipLaunchKernelGGL(xeng_cmac_batch_kernel<IN_CI4>, grid, block, 0, stream, jobs_dev, items_dev, queues, counters_dev); break;
     case IN_CF32: hipLaunchKernelGGL(xeng_cmac_batch_kernel<IN_CF32>, grid, block, 0, stream, jobs_dev, items_dev, queues, counters_dev); break;
+    default: return (int)hipErrorInvalidValue;
+    }
+    return (int)hipGetLastError();
+}
+
+int launch_cmac_batch_gen(const XJob *jobs_dev, const XGenQueues &g, unsigned int *counters_dev, int in_fmt,
+                          int nblocks, hipStream_t stream)
+{
+    if (nblocks <= 0) return 0;
+    const dim3 grid(nblocks), block(NTHREADS);
+    switch (in_fmt) {
+    case IN_CI8: hipLaunchKernelGGL(xeng_cmac_batch_gen_kernel<IN_CI8>, grid, block, 0, stream, jobs_dev, g, counters_dev); break;
+    case IN_CI4: hipLaunchKernelGGL(xeng_cmac_batch_gen_kernel<IN_CI4>, grid, block, 0, stream, jobs_dev, g, counters_dev); break;
+    case IN_CF32: hipLaunchKernelGGL(xeng_cmac_batch_gen_kernel<IN_CF32>, grid, block, 0, stream, jobs_dev, g, counters_dev); break;
     default: return (int)hipErrorInvalidValue;
     }
     return (int)hipGetLastError();

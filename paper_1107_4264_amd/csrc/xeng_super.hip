@@ -32,12 +32,13 @@ constexpr int SP_CONV = SP_TB * SP_CROW;   // widened bytes per block
 // of the row / column segment; NA / NB copy instructions (1 KiB each) per block for them;
 // DPW copies per wave per block (NA / 8 row copies and one column copy, the column copies
 // repeated by two waves when NB = 4); UB raw bytes of one 16-byte widened chunk.
-template <int IN>
+// Variant V (chosen by the autotuner): bit 0 keeps one block fewer in the raw ring.
+template <int IN, int V = 0>
 struct SGeo {
     static constexpr int BPS = IN == IN_CI8 ? 2 : 1;
     static constexpr int AROW = 256 * BPS, BROW = 128 * BPS;
     static constexpr int RAW = SP_TB * (AROW + BROW);
-    static constexpr int RING = 4;  // measured: 4 slots beat 3, 5, 6 and 8 (4-bit, 1024 inputs)
+    static constexpr int RING = 4 - (V & 1);  // measured: 4 slots beat 3, 5, 6 and 8 (4-bit, 1024 inputs)
     static constexpr int LDS = RING * RAW + 2 * SP_CONV;
     static constexpr int NA = SP_TB * AROW / 1024, NB = SP_TB * BROW / 1024;
     static constexpr int DPW = NA / 8 + 1;
@@ -176,10 +177,10 @@ __device__ __forceinline__ void descale_store(const XJob &p, int f, int lane, Ac
     store_all<ACC, S>(p, f, lane, acc, row_base, col_base);
 }
 
-template <int ACC, int IN, int TRI, int W>
+template <int ACC, int IN, int TRI, int W, int V>
 __device__ __forceinline__ void run_wave_super(const XJob &p, int lane)
 {
-    using Gs = SGeo<IN>;
+    using Gs = SGeo<IN, V>;
     constexpr int RING = Gs::RING, DPW = Gs::DPW, NKS = SP_TB / COp<ACC>::KS;
     constexpr int NAW = Gs::NA / 8;    // row-segment copies per wave per block
     static_assert(NKS >= 1 && SP_TB % COp<ACC>::KS == 0, "whole K-steps per block");
@@ -339,41 +340,46 @@ __device__ __forceinline__ void run_wave_super(const XJob &p, int lane)
     wait_vm<0>();
 }
 
-template <int ACC, int IN, int TRI>
+template <int ACC, int IN, int TRI, int V>
 __global__ __launch_bounds__(CT, 1) void xeng_super_kernel(XJob p)
 {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     switch (wave) {
-    case 0: run_wave_super<ACC, IN, TRI, 0>(p, lane); break;
-    case 1: run_wave_super<ACC, IN, TRI, 1>(p, lane); break;
-    case 2: run_wave_super<ACC, IN, TRI, 2>(p, lane); break;
-    case 3: run_wave_super<ACC, IN, TRI, 3>(p, lane); break;
-    case 4: run_wave_super<ACC, IN, TRI, 4>(p, lane); break;
-    case 5: run_wave_super<ACC, IN, TRI, 5>(p, lane); break;
-    case 6: run_wave_super<ACC, IN, TRI, 6>(p, lane); break;
-    default: run_wave_super<ACC, IN, TRI, 7>(p, lane); break;
+    case 0: run_wave_super<ACC, IN, TRI, 0, V>(p, lane); break;
+    case 1: run_wave_super<ACC, IN, TRI, 1, V>(p, lane); break;
+    case 2: run_wave_super<ACC, IN, TRI, 2, V>(p, lane); break;
+    case 3: run_wave_super<ACC, IN, TRI, 3, V>(p, lane); break;
+    case 4: run_wave_super<ACC, IN, TRI, 4, V>(p, lane); break;
+    case 5: run_wave_super<ACC, IN, TRI, 5, V>(p, lane); break;
+    case 6: run_wave_super<ACC, IN, TRI, 6, V>(p, lane); break;
+    default: run_wave_super<ACC, IN, TRI, 7, V>(p, lane); break;
     }
 }
 
-template <int ACC, int IN, int TRI>
+template <int ACC, int IN, int TRI, int V>
 int launch_super_kind(XJob job, int cus, hipStream_t stream)
 {
-    constexpr int LDS = SGeo<IN>::LDS;
-    if (int e = allow_lds_on_device<xeng_super_kernel<ACC, IN, TRI>>(LDS)) return e;
+    constexpr int LDS = SGeo<IN, V>::LDS;
+    if (int e = allow_lds_on_device<xeng_super_kernel<ACC, IN, TRI, V>>(LDS)) return e;
     const int ns = job.ntile_side;
     job.nitems = (int64_t)job.nwindows * job.nchan * (TRI ? ns : ns * (ns - 1));
     job.grid = job.nitems < cus ? job.nitems : cus;
     if (job.grid <= 0) return 0;
-    hipLaunchKernelGGL((xeng_super_kernel<ACC, IN, TRI>), dim3((unsigned)job.grid), dim3(CT), LDS, stream, job);
+    hipLaunchKernelGGL((xeng_super_kernel<ACC, IN, TRI, V>), dim3((unsigned)job.grid), dim3(CT), LDS, stream, job);
     return (int)hipGetLastError();
 }
 
 template <int ACC, int IN>
 int launch_super_pair(const XJob &job, int cus, hipStream_t stream)
 {
-    if (int e = launch_super_kind<ACC, IN, 1>(job, cus, stream)) return e;
-    return launch_super_kind<ACC, IN, 0>(job, cus, stream);
+    if (job.variant == 1) {
+        if (int e = launch_super_kind<ACC, IN, 1, 1>(job, cus, stream)) return e;
+        return launch_super_kind<ACC, IN, 0, 1>(job, cus, stream);
+    }
+    if (job.variant != 0) return (int)hipErrorInvalidValue;
+    if (int e = launch_super_kind<ACC, IN, 1, 0>(job, cus, stream)) return e;
+    return launch_super_kind<ACC, IN, 0, 0>(job, cus, stream);
 }
 
 }  // namespace

@@ -20,12 +20,13 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "xcorr.h")
 
 # enumerators of xcorr.h
 IN_CI8, IN_CI4, IN_CF32 = 0, 1, 2
-ACC_F32_CMAC, ACC_I8_MMA_I32, ACC_F16_MMA_F32, ACC_F8E4M3_MMA_F32 = 0, 1, 2, 3
+ACC_F32_CMAC, ACC_I8_MMA_I32, ACC_F16_MMA_F32, ACC_F8E4M3_MMA_F32, ACC_F32_MMA_F32, ACC_F6E3M2_MMA_F32 = range(6)
 OUT_CI32, OUT_CI64, OUT_C64, OUT_C128 = 0, 1, 2, 3
 OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_OOM, ERR_HIP, ERR_RANGE = 0, -1, -2, -3, -4, -5
 
 IN_NAMES = {"ci8": IN_CI8, "ci4": IN_CI4, "cf32": IN_CF32}
-ACC_NAMES = {"f32": ACC_F32_CMAC, "i8": ACC_I8_MMA_I32, "f16": ACC_F16_MMA_F32, "f8": ACC_F8E4M3_MMA_F32}
+ACC_NAMES = {"f32": ACC_F32_CMAC, "i8": ACC_I8_MMA_I32, "f16": ACC_F16_MMA_F32, "f8": ACC_F8E4M3_MMA_F32,
+             "f32m": ACC_F32_MMA_F32, "f6": ACC_F6E3M2_MMA_F32}
 
 
 class XcorrError(RuntimeError):
@@ -70,7 +71,14 @@ def _load():
         "xcorr_set_window": (c_int, [c_vp, c_int]),
         "xcorr_stream_set_window": (c_int, [c_vp, c_int]),
         "xcorr_autotune": (c_int, [c_vp, c_vp, c_vp, c_vp, c_int]),
-        "xcorr_autotune_lookup": (c_int, [c_int, c_int, c_int, c_int, c_int, c_int, c_int]),
+        "xcorr_autotune_lookup": (c_int, [ctypes.c_char_p, c_int, c_int, c_int, c_int, c_int, c_int, c_int,
+                                          ctypes.POINTER(c_int), ctypes.POINTER(c_int)]),
+        "xcorr_autotune_results": (c_int, [c_vp, c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_int),
+                                           ctypes.POINTER(c_int), ctypes.POINTER(ctypes.c_double)]),
+        "xcorr_set_staging": (c_int, [c_vp, c_int]),
+        "xcorr_get_staging": (c_int, [c_vp]),
+        "xcorr_set_variant": (c_int, [c_vp, c_int]),
+        "xcorr_get_variant": (c_int, [c_vp]),
         "xcorr_autotune_save": (c_int, [ctypes.c_char_p]),
         "xcorr_autotune_load": (c_int, [ctypes.c_char_p]),
         "xcorr_autotune_clear": (None, []),
@@ -165,8 +173,39 @@ def xcorr_autotune(h, in_ptr, out_ptr, stream_ptr, reps=3):
     return _check(_lib.xcorr_autotune(h, in_ptr, out_ptr, stream_ptr, reps))
 
 
-def xcorr_autotune_lookup(nstation, npol, nchan, ntime, in_dtype, acc_dtype, max_abs=0):
-    return _check(_lib.xcorr_autotune_lookup(nstation, npol, nchan, ntime, in_dtype, acc_dtype, max_abs))
+def xcorr_autotune_lookup(nstation, npol, nchan, ntime, in_dtype, acc_dtype, max_abs=0, arch=None, full=False):
+    """Tile cached for the job's class (0: none); with full=True, (tile, staging, variant)."""
+    st, var = ctypes.c_int(0), ctypes.c_int(0)
+    t = _check(_lib.xcorr_autotune_lookup(arch.encode() if arch else None, nstation, npol, nchan, ntime, in_dtype,
+                                          acc_dtype, max_abs, ctypes.byref(st), ctypes.byref(var)))
+    return (t, st.value, var.value) if full else t
+
+
+def xcorr_autotune_results(h):
+    """Shapes timed by the handle's last autotune: list of dicts (tile, staging, variant, us)."""
+    n = _check(_lib.xcorr_autotune_results(h, -1, None, None, None, None))
+    res = []
+    for k in range(n):
+        t, st, var, us = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        _lib.xcorr_autotune_results(h, k, ctypes.byref(t), ctypes.byref(st), ctypes.byref(var), ctypes.byref(us))
+        res.append({"tile": t.value, "staging": st.value, "variant": var.value, "us": us.value})
+    return res
+
+
+def xcorr_set_staging(h, staging):
+    return _check(_lib.xcorr_set_staging(h, staging))
+
+
+def xcorr_get_staging(h):
+    return _check(_lib.xcorr_get_staging(h))
+
+
+def xcorr_set_variant(h, variant):
+    return _check(_lib.xcorr_set_variant(h, variant))
+
+
+def xcorr_get_variant(h):
+    return _check(_lib.xcorr_get_variant(h))
 
 
 def xcorr_autotune_save(path):
@@ -263,6 +302,7 @@ def xcorr_batch_destroy(b):
     _lib.xcorr_batch_destroy(b)
 
 
+
 def xcorr_stream_create(nstation, npol, nchan, chunk_ntime, in_dtype, acc_dtype):
     s = _lib.xcorr_stream_create(nstation, npol, nchan, chunk_ntime, in_dtype, acc_dtype)
     if not s:
@@ -344,7 +384,7 @@ class Correlator:
     ('ci8', 'ci4', 'cf32' / 'f32', 'i8', 'f16', 'f8')."""
 
     def __init__(self, nstation, npol, nchan, ntime, in_dtype="ci8", acc="f16", max_abs=None, tile=None,
-                 window=None):
+                 window=None, staging=None, variant=None):
         self.nstation, self.npol, self.nchan, self.ntime = nstation, npol, nchan, ntime
         self.in_dtype = IN_NAMES.get(in_dtype, in_dtype)
         self.acc = ACC_NAMES.get(acc, acc)
@@ -353,12 +393,24 @@ class Correlator:
             xcorr_set_max_abs(self.h, int(max_abs))
         if window is not None:
             xcorr_set_window(self.h, int(window))
+        if staging is not None:
+            xcorr_set_staging(self.h, int(staging))
         if tile is not None:
             xcorr_set_tile(self.h, int(tile))
+        if variant is not None:
+            xcorr_set_variant(self.h, int(variant))
 
     @property
     def tile(self):
         return xcorr_get_tile(self.h)
+
+    @property
+    def staging(self):
+        return xcorr_get_staging(self.h)
+
+    @property
+    def variant(self):
+        return xcorr_get_variant(self.h)
 
     def close(self):
         if self.h:

@@ -13,6 +13,22 @@ def say(*a):
     sys.stdout.flush()
 
 
+# Largest sample component the low-precision operand types hold exactly (8-bit samples on
+# these paths need the bound declared).
+LOWBIT = {"f8": 16, "f6": 8}
+
+
+def low_dist(acc, default):
+    """Sample distribution for 8-bit samples on path acc: uniform within the operand type's
+    exact range on the fp8 / fp6 paths, `default` otherwise."""
+    m = LOWBIT.get(acc)
+    return ("uniform", -m, m) if m else default
+
+
+def low_max_abs(acc):
+    return LOWBIT.get(acc)
+
+
 def device():
     import torch
 

@@ -324,3 +324,35 @@ def test_super_tiles_with_requested_windows():
     assert p["tile"] == 512 and p["nwindows"] == 2 and p["out_dtype"] == X.OUT_CI64
     p = X.xcorr_plan(256, 2, 2, 10 * lim, X.IN_CI4, X.ACC_I8_MMA_I32, 0, 0, lim)
     assert p["tile"] == 512
+
+
+def test_fp32_matrix_core_path_plans():
+    """The fp32 matrix-core path: fp32 windows like the fp16 path, tiled kernel only, integer
+    samples only."""
+    assert X.xcorr_window_limit(X.IN_CI8, X.ACC_F32_MMA_F32, 128) == 512
+    assert X.xcorr_window_limit(X.IN_CI4, X.ACC_F32_MMA_F32, 8) == 131072
+    p = X.xcorr_plan(128, 2, 4, 1000, X.IN_CI8, X.ACC_F32_MMA_F32, 18)
+    assert p["tile"] == 128 and p["out_dtype"] == X.OUT_C64 and p["nwindows"] == 1
+    assert X.xcorr_plan(16, 2, 4, 100, X.IN_CI8, X.ACC_F32_MMA_F32, 0)["tile"] == 64
+    assert X.xcorr_plan(40, 2, 4, 1100, X.IN_CI8, X.ACC_F32_MMA_F32, 0)["out_dtype"] == X.OUT_C128
+    for tile in (256, 512):
+        with pytest.raises(X.XcorrError):
+            X.xcorr_plan(128, 2, 4, 100, X.IN_CI8, X.ACC_F32_MMA_F32, 0, tile)
+    with pytest.raises(X.XcorrError) as e:
+        X.xcorr_plan(8, 2, 1, 10, X.IN_CF32, X.ACC_F32_MMA_F32, 0)
+    assert e.value.code == X.ERR_UNSUPPORTED
+
+
+def test_fp6_path_plans():
+    """fp6 e3m2 holds the integers of [-8, 8]: CI4 always, CI8 only with a declared bound of
+    at most 8; fp32 windows; the tiled kernel."""
+    assert X.xcorr_window_limit(X.IN_CI4, X.ACC_F6E3M2_MMA_F32, 8) == 131072
+    p = X.xcorr_plan(512, 2, 256, 4096, X.IN_CI4, X.ACC_F6E3M2_MMA_F32, 0)
+    assert p["tile"] == 128 and p["out_dtype"] == X.OUT_C64 and p["max_abs"] == 8
+    assert X.xcorr_plan(8, 2, 1, 10, X.IN_CI8, X.ACC_F6E3M2_MMA_F32, 8)["out_dtype"] == X.OUT_C64
+    with pytest.raises(X.XcorrError) as e:
+        X.xcorr_plan(8, 2, 1, 10, X.IN_CI8, X.ACC_F6E3M2_MMA_F32, 9)
+    assert e.value.code == X.ERR_UNSUPPORTED
+    for tile in (256, 512):
+        with pytest.raises(X.XcorrError):
+            X.xcorr_plan(512, 2, 4, 100, X.IN_CI4, X.ACC_F6E3M2_MMA_F32, 0, tile)

@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 from paper_1107_4264_amd import synth
-from tests.gpu_util import as_exact_int, device, run_xeng, say
+from tests.gpu_util import as_exact_int, device, low_dist, low_max_abs, run_xeng, say
 
 pytestmark = pytest.mark.gpu
 
@@ -22,21 +22,21 @@ JOBS = [
 ]
 
 
-@pytest.mark.parametrize("acc", ["f32", "i8", "f16", "f8"])
+@pytest.mark.parametrize("acc", ["f32", "i8", "f16", "f8", "f32m", "f6"])
 def test_batch_matches_oracle(oracle_mod, acc):
     import torch
 
     from paper_1107_4264_amd import xcorr as X
 
     dev = device()
-    dist = ("uniform", -16, 16) if acc == "f8" else ("gauss", 50.0, 127)
+    dist = low_dist(acc, ("gauss", 50.0, 127))
     xs, wants = [], []
     for k, (ns, npol, F, T) in enumerate(JOBS):
         x = synth.voltages_np(synth.SEED_BASE + 3 + 16 * k, T, F, ns * npol, dist)
         xs.append(x)
         wants.append(oracle_mod.xcorr(x, ns, npol))
     say("batch", acc, "jobs", len(JOBS))
-    b = X.Batch(JOBS, "ci8", acc, max_abs=16 if acc == "f8" else None)
+    b = X.Batch(JOBS, "ci8", acc, max_abs=low_max_abs(acc))
     assert X.xcorr_batch_items(b.b) > 0
     outs = b.run([torch.from_numpy(x).to(dev) for x in xs])
     torch.cuda.synchronize()
@@ -45,7 +45,7 @@ def test_batch_matches_oracle(oracle_mod, acc):
         assert np.array_equal(got, want), f"job {k} {JOBS[k]}"
     # same bits as launching each job alone
     for k, (ns, npol, F, T) in enumerate(JOBS[:3]):
-        single, _ = run_xeng(xs[k], ns, npol, "ci8", acc, max_abs=16 if acc == "f8" else None)
+        single, _ = run_xeng(xs[k], ns, npol, "ci8", acc, max_abs=low_max_abs(acc))
         assert np.array_equal(single, outs[k].cpu().numpy())
     # run twice: same bits (counters and zero fills are reset per run)
     outs2 = b.run([torch.from_numpy(x).to(dev) for x in xs])
@@ -68,7 +68,7 @@ def test_batch_ci4(oracle_mod):
         p = synth.pack_ci4(v)
         xs.append(p)
         wants.append(oracle_mod.xcorr(p, ns, npol, fmt=oracle_mod.CI4))
-    for acc in ["i8", "f16", "f8"]:
+    for acc in ["i8", "f16", "f8", "f32m", "f6"]:
         say("batch ci4", acc)
         b = X.Batch(jobs, "ci4", acc)
         outs = b.run([torch.from_numpy(x).to(dev) for x in xs])

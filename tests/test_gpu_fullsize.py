@@ -1,7 +1,7 @@
 """GPU parity at the stated sizes of the benchmark workloads, on sampled channels the oracle
 computes one by one: 256 inputs x 1024 channels x 1000 8-bit samples (FP32 CMAC, fp16 and
 int8 matrix cores) and 1024 inputs x 256 channels x 4096 4-bit samples (int8 and fp8
-matrix cores on super-tiles).  Inputs come from the same seeded generator as the
+matrix cores on super-tiles, fp6 on 128-tiles).  Inputs come from the same seeded generator as the
 benchmark, evaluated on the device for the GPU run and on the host for the sampled
 channels."""
 
@@ -66,10 +66,10 @@ def test_n1024_ci4_full_size(oracle_mod):
     chans = [0, 77, 190, F - 1]
     want = oracle_mod.xcorr(synth.pack_ci4(synth.voltages_np(seed, T, F, nin, dist, chans=chans)), ns, npol,
                             fmt=oracle_mod.CI4)
-    for acc in ("i8", "f8"):
+    for acc in ("i8", "f8", "f6"):
         say("full size 1024 inputs", acc)
         c = X.Correlator(ns, npol, F, T, "ci4", acc)
-        assert c.tile == 512
+        assert c.tile == (128 if acc == "f6" else 512)
         out = c.run(x)
         torch.cuda.synchronize()
         _sampled(oracle_mod, out, want, chans, f"n1024/{acc}")

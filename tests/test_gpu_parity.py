@@ -9,11 +9,11 @@ import pytest
 
 from paper_1107_4264_amd import synth
 from tests import refmath
-from tests.gpu_util import as_exact_int, device, run_xeng, say
+from tests.gpu_util import as_exact_int, device, low_dist, low_max_abs, run_xeng, say
 
 pytestmark = pytest.mark.gpu
 
-PATHS = ["f32", "i8", "f16", "f8"]
+PATHS = ["f32", "i8", "f16", "f8", "f32m", "f6"]
 
 
 def _oracle_ci8(oracle_mod, x, ns, npol, chans=None):
@@ -60,10 +60,10 @@ RAGGED = [
 @pytest.mark.parametrize("shape", RAGGED, ids=lambda s: "x".join(map(str, s)))
 def test_ragged_shapes_ci8(oracle_mod, acc, shape):
     ns, npol, F, T = shape
-    dist = ("uniform", -16, 16) if acc == "f8" else ("gauss", 40.0, 127)
+    dist = low_dist(acc, ("gauss", 40.0, 127))
     x = synth.voltages_np(1000 + ns * 31 + T, T, F, ns * npol, dist)
     say("ragged ci8", acc, shape)
-    got, _ = run_xeng(x, ns, npol, "ci8", acc, max_abs=16 if acc == "f8" else None)
+    got, _ = run_xeng(x, ns, npol, "ci8", acc, max_abs=low_max_abs(acc))
     _check_exact(got, _oracle_ci8(oracle_mod, x, ns, npol), f"ragged/{acc}/{shape}")
 
 
@@ -80,7 +80,7 @@ def test_ragged_shapes_ci4(oracle_mod, acc, shape):
     _check_exact(got, want, f"ci4/{acc}/{shape}")
 
 
-@pytest.mark.parametrize("acc", ["f32", "f16", "i8"])
+@pytest.mark.parametrize("acc", ["f32", "f16", "i8", "f32m"])
 def test_extreme_values(oracle_mod, acc):
     """Every sample at the bound of the format: -128 (or -127 on the int8 path) and 127."""
     ns, npol, F, T = 20, 2, 3, 200
@@ -92,7 +92,7 @@ def test_extreme_values(oracle_mod, acc):
     _check_exact(got, _oracle_ci8(oracle_mod, x, ns, npol), f"extreme/{acc}")
 
 
-@pytest.mark.parametrize("acc,T", [("f16", 1100), ("f32", 1300), ("i8", 70000)])
+@pytest.mark.parametrize("acc,T", [("f16", 1100), ("f32", 1300), ("i8", 70000), ("f32m", 1100)])
 def test_multiple_windows(oracle_mod, acc, T):
     """Integrations longer than one exact window: windows summed into int64 / fp64."""
     ns, npol, F = 5, 2, 2
@@ -173,7 +173,7 @@ def test_deterministic(acc):
 def test_point_source_small(oracle_mod):
     ns, npol, F, T = 40, 2, 6, 300
     x, a, s = synth.point_source_np(0xC0FFEE, T, F, ns * npol)
-    for acc in ["f32", "f16", "i8"]:
+    for acc in ["f32", "f16", "i8", "f32m"]:
         got, _ = run_xeng(x, ns, npol, "ci8", acc, max_abs=126)
         g = refmath.as_complex_out(as_exact_int(got))
         ac = a[:, 0] + 1j * a[:, 1]

@@ -8,12 +8,12 @@ import numpy as np
 import pytest
 
 from paper_1107_4264_amd import synth
-from tests.gpu_util import as_exact_int, device, say
+from tests.gpu_util import as_exact_int, device, low_dist, low_max_abs, say
 
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("acc", ["i8", "f16", "f32", "f8"])
+@pytest.mark.parametrize("acc", ["i8", "f16", "f32", "f8", "f32m", "f6"])
 def test_stream_matches_oracle(oracle_mod, acc):
     import torch
 
@@ -21,11 +21,11 @@ def test_stream_matches_oracle(oracle_mod, acc):
 
     device()
     ns, npol, F, chunk, nchunk = 36, 2, 5, 96, 5
-    dist = ("uniform", -16, 16) if acc == "f8" else ("gauss", 60.0, 127)
+    dist = low_dist(acc, ("gauss", 60.0, 127))
     x = synth.voltages_np(4242, chunk * nchunk, F, ns * npol, dist)
     want = oracle_mod.xcorr(x, ns, npol)
     say("stream", acc)
-    st = X.Stream(ns, npol, F, chunk, "ci8", acc, max_abs=16 if acc == "f8" else None)
+    st = X.Stream(ns, npol, F, chunk, "ci8", acc, max_abs=low_max_abs(acc))
     chunks = [torch.from_numpy(np.ascontiguousarray(x[c * chunk:(c + 1) * chunk])).pin_memory()
               for c in range(nchunk)]
     out = st.begin()

@@ -16,7 +16,7 @@ import numpy as np
 import pytest
 
 from paper_1107_4264_amd import synth
-from tests.gpu_util import as_exact_int, device, say
+from tests.gpu_util import as_exact_int, device, low_dist, low_max_abs, say
 
 pytestmark = pytest.mark.gpu
 
@@ -107,7 +107,8 @@ def test_int8_window_bound_super(oracle_mod):
 # --------------------------------------------------------------- fp32 accumulators, 8-bit
 
 
-@pytest.mark.parametrize("acc,tile", [("f16", 64), ("f16", 128), ("f16", 256), ("f32", 64)])
+@pytest.mark.parametrize("acc,tile", [("f16", 64), ("f16", 128), ("f16", 256), ("f32", 64), ("f32m", 64),
+                                      ("f32m", 128)])
 def test_fp32_window_bound_ci8(oracle_mod, acc, tile):
     """-128 - 128i with max_abs 128: T = 512 puts the autocorrelations at 2^24 exactly (one
     fp32 window, c64); T = 513 needs two windows (fp64 totals, c128)."""
@@ -138,6 +139,24 @@ def constant_worst_ci4(T, F, nin):
     repeated)."""
     row = synth.pack_ci4(constant_worst(1, 1, nin, -8, 7))
     return np.broadcast_to(row, (T, F, nin)).copy()
+
+
+def test_fp6_window_bound_ci4(oracle_mod):
+    """4-bit samples at -8 - 8i on the fp6 path: T = 131072 (one fp32 window, c64) and
+    T = 131073 (two windows, c128)."""
+    from paper_1107_4264_amd import xcorr as X
+
+    ns, npol, F = 4, 2, 1
+    lim = X.xcorr_window_limit(X.IN_CI4, X.ACC_F6E3M2_MMA_F32, 8)
+    assert lim == 131072
+    for T, want_type in ((lim, X.OUT_C64), (lim + 1, X.OUT_C128)):
+        x = constant_worst_ci4(T, F, ns * npol)
+        say("fp6 window bound", T)
+        got, ot, _ = _run(x, ns, npol, "ci4", "f6")
+        assert ot == want_type
+        want = oracle_mod.xcorr(x, ns, npol, fmt=oracle_mod.CI4)
+        assert int(want[..., 0].max()) == T * 128
+        _check(got, want, f"fp6-bound/{T}")
 
 
 @pytest.mark.parametrize("tile", [64, 512])
@@ -208,6 +227,9 @@ CASES = [
     ("ci4", "i8", 256, 2, 512),    # 4-bit super-tiles (scaled operands)
     ("ci4", "f8", 136, 2, 512),    # partial last super-row
     ("ci4", "i8", 70, 1, 128),
+    ("ci8", "f32m", 45, 2, 128),   # fp32 matrix cores
+    ("ci4", "f6", 70, 2, 128),     # fp6 e3m2
+    ("ci8", "f6", 33, 2, 64),
 ]
 
 
@@ -224,12 +246,12 @@ def test_requested_windows_match_oracle(oracle_mod, case, window):
         x = _pack(synth.voltages_np(synth.SEED_BASE + 90 + ns + window, T, F, ns * npol, ("uniform", -8, 7)))
         want = oracle_mod.xcorr(x, ns, npol, fmt=oracle_mod.CI4)
     else:
-        dist = ("uniform", -16, 16) if acc == "f8" else ("gauss", 50.0, 127)
+        dist = low_dist(acc, ("gauss", 50.0, 127))
         x = synth.voltages_np(synth.SEED_BASE + 91 + ns + window, T, F, ns * npol, dist)
         want = oracle_mod.xcorr(x, ns, npol)
     say("requested windows", case, window)
     # 8-bit samples on the fp8 path need a declared bound of at most 16
-    ma = 16 if (acc == "f8" and fmt == "ci8") else None
+    ma = low_max_abs(acc) if fmt == "ci8" else None
     got, ot, t = _run(x, ns, npol, fmt, acc, tile=tile, window=window, max_abs=ma)
     assert t == tile
     assert ot == (X.OUT_CI64 if acc == "i8" else X.OUT_C128)
