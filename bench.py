@@ -65,7 +65,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--ramp-seconds", type=float, default=0.3,
                     help="untimed run time per path before the warmup steps, so that clocks have settled")
-    ap.add_argument("--workload", default="n256-ci8", choices=sorted(WORKLOADS) + ["batch64", "stream"])
+    ap.add_argument("--workload", default="n256-ci8", choices=sorted(WORKLOADS) + ["batch64", "stream", "fengine"])
     ap.add_argument("--paths", default=None, help="comma-separated paths (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
@@ -97,6 +97,9 @@ def main():
         return bench_batch(args, dev)
     if args.workload == "stream":
         return bench_stream(args, dev)
+    if args.workload == "fengine":
+        print(json.dumps(bench_fengine(args, dev)), flush=True)
+        return
     w = WORKLOADS[args.workload]
     ns, npol, F, T = w["nstation"], w["npol"], w["nchan"], w["ntime"]
     nin = ns * npol
@@ -229,7 +232,94 @@ def main():
             del outs[k]
         del x
         line["small_array"] = bench_small(args, dev)
+        line["f_engine"] = bench_fengine(args, dev)
     print(json.dumps(line), flush=True)
+
+
+FENGINE = {
+    "name": "F-engine + corner turn: 256 inputs (128 stations x 2 pol), 1024-point transforms, 1000 frames "
+            "(1,024,000 complex 8-bit samples per input, gaussian sigma=20), gain 0.5/sqrt(1024), requantised "
+            "to 8-bit [frame][channel][input]",
+    "nstation": 128, "npol": 2, "nchan": 1024, "nframes": 1000, "sigma": 20.0, "seed_index": 5,
+}
+
+
+def bench_fengine(args, dev):
+    """The F-engine on the benchmark's X-engine input shape: time per pass, HBM bytes
+    (input read once, requantised output written once) per second, and the FX chain (F-engine
+    then the fp16 X-engine) per pass.  The CPU baseline leg runs the F-engine oracle on the
+    first frames of every input and compares the requantised samples."""
+    import numpy as np
+    import torch
+
+    from paper_1107_4264_amd import synth
+    from paper_1107_4264_amd import xcorr as X
+
+    w = FENGINE
+    ns, npol, F, T = w["nstation"], w["npol"], w["nchan"], w["nframes"]
+    nin = ns * npol
+    seed = synth.SEED_BASE + w["seed_index"]
+    dist = ("gauss", w["sigma"], 127)
+    gain = 0.5 / F ** 0.5
+    v = synth.voltages_torch(seed, T * F, 1, nin, dist, dev)          # [nsamp][1][nin][2]
+    x = v[:, 0].permute(1, 0, 2).contiguous()                           # [nin][nsamp][2]
+    del v
+    e = X.FEngine(ns, npol, F, T, gain)
+    out = e.empty_out(dev)
+    c = X.Correlator(ns, npol, F, T, "ci8", "f16", max_abs=127)
+    vis = c.empty_out(dev)
+    stream = torch.cuda.current_stream()
+    steps = max(1, min(args.steps, 50))
+
+    def timed(fn):
+        for _ in range(max(args.warmup, 3)):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    ms_f = timed(lambda: e.run(x, out))
+    ms_fx = timed(lambda: (e.run(x, out), c.run(out, vis)))
+    nbytes = X.xcorr_fengine_in_bytes(e.e) + X.xcorr_fengine_out_bytes(e.e, 0)
+    flops = 5.0 * F * np.log2(F) * nin * T
+    res = {
+        "workload": w["name"],
+        "ms_per_pass": round(ms_f, 5),
+        "hbm_gbps": round(nbytes / (ms_f * 1e-3) / 1e9, 1),
+        "roofline": {"bound": "hbm", "achieved": round(nbytes / (ms_f * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": round(nbytes / (ms_f * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)},
+        "fft_tflops": round(flops / (ms_f * 1e-3) / 1e12, 3),
+        "fx_chain_ms_per_pass": round(ms_fx, 5),
+        "xengine_path": "f16 mfma",
+    }
+    print(f"[bench] F-engine: {ms_f:.4f} ms per pass, {res['hbm_gbps']} GB/s; F + X: {ms_fx:.4f} ms",
+          file=sys.stderr, flush=True)
+    if not args.no_cpu_baseline:
+        from oracle import fengine as FE
+
+        nf = 4  # first frames of every input (the generator's leading index is the sample)
+        hv = synth.voltages_np(seed, nf * F, 1, nin, dist)
+        hx = np.ascontiguousarray(np.transpose(hv[:, 0], (1, 0, 2)))
+        t0 = time.perf_counter()
+        spec = FE.channelise(hx, F, gain)
+        want = FE.requantise(spec)
+        dt = time.perf_counter() - t0
+        got = out[:nf].cpu().numpy()
+        diff = np.abs(got.astype(np.int16) - want)
+        res["cpu_baseline"] = {"value": round(5.0 * F * np.log2(F) * nin * nf / dt / 1e12, 6), "unit": "TFLOPS",
+                               "cores": 1, "kind": "oracle",
+                               "sample": f"first {nf} frames of all {nin} inputs, {dt:.3f} s"}
+        res["parity"] = (f"requantised samples of the sampled frames: {int((diff != 0).sum())} of {diff.size} "
+                         f"components differ from the oracle, by at most {int(diff.max())} (fp32 against fp64 "
+                         f"rounding at the half-integer boundaries)")
+    e.close()
+    c.close()
+    return res
 
 
 def launches_per_step(plan):

@@ -367,6 +367,39 @@ int64_t xcorr_window_limit(xcorr_in_dtype in_dtype, xcorr_acc_dtype acc_dtype, i
  * (Sec. 4.2), in exact integer arithmetic.  Returns XCORR_ERR_INVALID_ARG for g < 0. */
 int xcorr_tile_coords(int64_t g, int64_t *bx, int64_t *by);
 
+/* ------------------------------------------------------------------ F-engine and corner turn */
+
+/*
+ * The F-engine of the FX correlator (Sec. 2.1): every input's digitised complex signal is
+ * Fourier transformed nchan samples at a time, one nchan-point DFT per input every nchan
+ * samples, and the corner turn reorders the spectra from station-major to the
+ * channel-major order the X-engine reads (Sec. 4.1).  Output channel k of frame t is DFT bin
+ * k of samples t nchan .. t nchan + nchan - 1, X[k] = sum_n x[n] exp(-2 pi i k n / nchan)
+ * (natural order, no window or filter bank), times `gain`, requantised to XCORR_IN_CI8
+ * samples: each component rounded half away from zero and clipped to [-127, 127], so the
+ * output can go straight to any X-engine path.
+ *
+ * Layouts:
+ *   input   x[nin][nframes * nchan] complex int8 (re, im), nin = nstation * npol (input
+ *           station * npol + pol), each input's samples contiguous; 4-byte aligned;
+ *   output  [nframes][nchan][nin] complex int8 (re, im): xcorr_create(nstation, npol,
+ *           nchan, nframes, XCORR_IN_CI8, ...) reads it as is;
+ *   spectra (xcorr_fengine_run_spectra) the same order as complex float (re, im), gain
+ *           applied, not rounded.
+ * nchan a power of two in 64..2048; gain > 0.  Device pointers owned by the caller; runs are
+ * asynchronous on `stream`; the current device must be the one the object was created on.
+ * Computed in fp32: a value within a few fp32 rounding errors of a rounding boundary may
+ * land on either neighbouring integer.
+ */
+typedef struct xcorr_fengine xcorr_fengine_t;
+
+xcorr_fengine_t *xcorr_fengine_create(int nstation, int npol, int nchan, int nframes, float gain);
+size_t xcorr_fengine_in_bytes(const xcorr_fengine_t *e);
+size_t xcorr_fengine_out_bytes(const xcorr_fengine_t *e, int spectra);
+int xcorr_fengine_run(xcorr_fengine_t *e, const void *in, void *out, hipStream_t stream);
+int xcorr_fengine_run_spectra(xcorr_fengine_t *e, const void *in, void *out, hipStream_t stream);
+void xcorr_fengine_destroy(xcorr_fengine_t *e);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1031,3 +1031,89 @@ void xcorr_graph_destroy(hipGraphExec_t exec)
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------ F-engine
+
+struct xcorr_fengine {
+    int nstation = 0, npol = 0, nchan = 0, nframes = 0, nin = 0;
+    float gain = 1.0f;
+    int device = 0;
+};
+
+extern "C" {
+
+xcorr_fengine_t *xcorr_fengine_create(int nstation, int npol, int nchan, int nframes, float gain)
+{
+    if (nstation < 1 || (npol != 1 && npol != 2) || nframes < 0) {
+        fail(XCORR_ERR_INVALID_ARG, "need nstation >= 1, npol in {1, 2}, nframes >= 0");
+        return nullptr;
+    }
+    if (nchan < 64 || nchan > 2048 || (nchan & (nchan - 1))) {
+        fail(XCORR_ERR_INVALID_ARG, "nchan (the transform length) must be a power of two in 64..2048");
+        return nullptr;
+    }
+    if (!(gain > 0.0f) || gain > 1e30f) {
+        fail(XCORR_ERR_INVALID_ARG, "gain must be a positive finite number");
+        return nullptr;
+    }
+    const int64_t nin = (int64_t)nstation * npol;
+    if (nin > 65536 || (int64_t)nframes * nchan * nin > ((int64_t)1 << 40)) {
+        fail(XCORR_ERR_RANGE, "too many inputs or samples");
+        return nullptr;
+    }
+    int dev = 0;
+    const hipError_t he = hipGetDevice(&dev);
+    if (he != hipSuccess) {
+        hip_fail((int)he, "hipGetDevice");
+        return nullptr;
+    }
+    xcorr_fengine *e = new (std::nothrow) xcorr_fengine;
+    if (!e) {
+        fail(XCORR_ERR_OOM, "host allocation");
+        return nullptr;
+    }
+    e->nstation = nstation;
+    e->npol = npol;
+    e->nchan = nchan;
+    e->nframes = nframes;
+    e->nin = (int)nin;
+    e->gain = gain;
+    e->device = dev;
+    return e;
+}
+
+size_t xcorr_fengine_in_bytes(const xcorr_fengine_t *e)
+{
+    return e ? (size_t)e->nin * e->nframes * e->nchan * 2 : 0;
+}
+
+size_t xcorr_fengine_out_bytes(const xcorr_fengine_t *e, int spectra)
+{
+    return e ? (size_t)e->nframes * e->nchan * e->nin * (spectra ? 8 : 2) : 0;
+}
+
+static int fengine_run(xcorr_fengine_t *e, const void *in, void *out, hipStream_t stream, bool spectra)
+{
+    if (!e) return fail(XCORR_ERR_INVALID_ARG, "null F-engine");
+    if (e->nframes == 0) return XCORR_OK;
+    if (!in || !out) return fail(XCORR_ERR_INVALID_ARG, "null input or output");
+    if ((uintptr_t)in % 4 != 0) return fail(XCORR_ERR_INVALID_ARG, "the input must be 4-byte aligned");
+    if (int rc = check_device(e->device)) return rc;
+    const int rc = launch_fengine(in, out, e->nin, e->nchan, (int64_t)e->nframes * e->nchan, e->nframes, e->gain,
+                                  spectra, stream);
+    return rc ? hip_fail(rc, "F-engine launch") : XCORR_OK;
+}
+
+int xcorr_fengine_run(xcorr_fengine_t *e, const void *in, void *out, hipStream_t stream)
+{
+    return fengine_run(e, in, out, stream, false);
+}
+
+int xcorr_fengine_run_spectra(xcorr_fengine_t *e, const void *in, void *out, hipStream_t stream)
+{
+    return fengine_run(e, in, out, stream, true);
+}
+
+void xcorr_fengine_destroy(xcorr_fengine_t *e) { delete e; }
+
+}  // extern "C"

@@ -124,6 +124,14 @@ int launch_cmac_batch_gen(const XJob *jobs_dev, const XGenQueues &g, unsigned in
                           int nblocks, hipStream_t stream);
 
 
+
+// F-engine (fengine.hip): per input and frame an nchan-point DFT of the complex 8-bit
+// samples in[nin][nsamp] (frame t = samples t nchan .. t nchan + nchan - 1), times gain,
+// written corner-turned as out[t][k][i]: requantised int8 (re, im) pairs, or with `spectra`
+// the complex fp32 values.  nchan a power of two in 64..2048.
+int launch_fengine(const void *in, void *out, int nin, int nchan, int64_t nsamp, int nframes, float gain,
+                   bool spectra, hipStream_t stream);
+
 // Number of compute units of the current device (for persistent grids).
 int device_cus();
 

@@ -207,12 +207,27 @@ __device__ __forceinline__ void load_rows(__amdgpu_buffer_rsrc_t rs, uint32_t ro
                 rows[u][0] = v[0]; rows[u][1] = v[1];
             }
         } else if constexpr (MODE == LOAD_WORD) {
-            constexpr int PER_WORD = 4 / T::BPC;
+            // Word-aligned rows: a chunk that lies inside the row is one wide load (the HSA
+            // runtime runs gfx9 and later in unaligned-access mode, so a 16-byte load needs
+            // only 4-byte alignment); the chunk that runs past the last input goes word by
+            // word, so that no load reaches beyond the row's last input.
+            if (i0 + T::CI <= nin) {
+                const uint32_t off = roff + (uint32_t)i0 * T::BPC;
+                if constexpr (T::LW == 4) {
+                    const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, 0);
+                    rows[u][0] = v[0]; rows[u][1] = v[1]; rows[u][2] = v[2]; rows[u][3] = v[3];
+                } else {
+                    const auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, (int)off, 0, 0);
+                    rows[u][0] = v[0]; rows[u][1] = v[1];
+                }
+            } else {
+                constexpr int PER_WORD = 4 / T::BPC;
 #pragma unroll
-            for (int k = 0; k < T::LW; ++k) {
-                const int ik = i0 + k * PER_WORD;
-                const uint32_t off = ik < nin ? roff + (uint32_t)ik * T::BPC : OOB;
-                rows[u][k] = __builtin_amdgcn_raw_buffer_load_b32(rs, (int)off, 0, 0);
+                for (int k = 0; k < T::LW; ++k) {
+                    const int ik = i0 + k * PER_WORD;
+                    const uint32_t off = ik < nin ? roff + (uint32_t)ik * T::BPC : OOB;
+                    rows[u][k] = __builtin_amdgcn_raw_buffer_load_b32(rs, (int)off, 0, 0);
+                }
             }
         } else {
 #pragma unroll

@@ -112,6 +112,12 @@ def _load():
         "xcorr_stream_capture": (c_int, [c_vp, c_int, c_vp, c_vp, ctypes.POINTER(c_vp)]),
         "xcorr_graph_launch": (c_int, [c_vp, c_vp]),
         "xcorr_graph_destroy": (None, [c_vp]),
+        "xcorr_fengine_create": (c_vp, [c_int, c_int, c_int, c_int, ctypes.c_float]),
+        "xcorr_fengine_in_bytes": (c_sz, [c_vp]),
+        "xcorr_fengine_out_bytes": (c_sz, [c_vp, c_int]),
+        "xcorr_fengine_run": (c_int, [c_vp, c_vp, c_vp, c_vp]),
+        "xcorr_fengine_run_spectra": (c_int, [c_vp, c_vp, c_vp, c_vp]),
+        "xcorr_fengine_destroy": (None, [c_vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -365,6 +371,33 @@ def xcorr_graph_destroy(exec_handle):
 
 # ------------------------------------------------------------------ torch convenience
 
+def xcorr_fengine_create(nstation, npol, nchan, nframes, gain):
+    e = _lib.xcorr_fengine_create(nstation, npol, nchan, nframes, float(gain))
+    if not e:
+        raise XcorrError(-1, last_error())
+    return e
+
+
+def xcorr_fengine_in_bytes(e):
+    return int(_lib.xcorr_fengine_in_bytes(e))
+
+
+def xcorr_fengine_out_bytes(e, spectra=0):
+    return int(_lib.xcorr_fengine_out_bytes(e, int(spectra)))
+
+
+def xcorr_fengine_run(e, in_ptr, out_ptr, stream_ptr):
+    return _check(_lib.xcorr_fengine_run(e, in_ptr, out_ptr, stream_ptr))
+
+
+def xcorr_fengine_run_spectra(e, in_ptr, out_ptr, stream_ptr):
+    return _check(_lib.xcorr_fengine_run_spectra(e, in_ptr, out_ptr, stream_ptr))
+
+
+def xcorr_fengine_destroy(e):
+    _lib.xcorr_fengine_destroy(e)
+
+
 def out_torch_dtype(out_type):
     import torch
 
@@ -605,3 +638,45 @@ class Graph:
             self.close()
         except Exception:
             pass
+
+
+class FEngine:
+    """F-engine and corner turn: int8 [nin][nframes * nchan][2] voltages -> int8
+    [nframes][nchan][nin][2] requantised spectra (the X-engine's input), or complex float
+    spectra with run(..., spectra=True)."""
+
+    def __init__(self, nstation, npol, nchan, nframes, gain):
+        self.nstation, self.npol, self.nchan, self.nframes = nstation, npol, nchan, nframes
+        self.nin = nstation * npol
+        self.e = xcorr_fengine_create(nstation, npol, nchan, nframes, gain)
+
+    def close(self):
+        if self.e:
+            xcorr_fengine_destroy(self.e)
+            self.e = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def empty_out(self, device="cuda", spectra=False):
+        import torch
+
+        if spectra:
+            return torch.empty((self.nframes, self.nchan, self.nin, 2), dtype=torch.float32, device=device)
+        return torch.empty((self.nframes, self.nchan, self.nin, 2), dtype=torch.int8, device=device)
+
+    def run(self, x, out=None, spectra=False, stream=None):
+        if not x.is_cuda:
+            raise ValueError("input must be a device tensor")
+        if x.numel() * x.element_size() != xcorr_fengine_in_bytes(self.e):
+            raise ValueError("input size does not match the F-engine")
+        if out is None:
+            out = self.empty_out(x.device, spectra)
+        if out.numel() * out.element_size() != xcorr_fengine_out_bytes(self.e, spectra):
+            raise ValueError("output buffer does not match the F-engine")
+        fn = xcorr_fengine_run_spectra if spectra else xcorr_fengine_run
+        fn(self.e, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream))
+        return out
