@@ -265,6 +265,26 @@ int xcorr_batch_out_type(const xcorr_batch_t *b, int job);
 int64_t xcorr_batch_items(const xcorr_batch_t *b);
 void xcorr_batch_destroy(xcorr_batch_t *b);
 
+/* For callers that cannot allocate memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation): the work of xcorr_batch_create(njobs, jobs,
+ * in_dtype, acc_dtype) + xcorr_batch_set_max_abs(max_abs) (max_abs 0: the format's default;
+ * 8-bit samples on the fp8 path need 1..16) + xcorr_batch_run(in, out, stream), in one
+ * call that allocates nothing on the host or the device and gives the same visibilities.
+ * The jobs that run on the tiled kernel take their work from a fixed workspace inside the
+ * library instead of allocated buffers: a job table, queue counters and the generated
+ * work list's counts, XCORR_NOALLOC_SCRATCH_BYTES per GPU, held from the first call on a
+ * GPU until the process ends.  The job table reaches it by kernel arguments and the
+ * counters are cleared on `stream` at every call, so the call only enqueues work and
+ * returns (nothing is read from host memory afterwards).  Every call on a GPU shares that
+ * GPU's workspace: calls that overlap on one GPU (on different streams, or from several
+ * threads without ordering) race and give wrong results; calls ordered on one stream are
+ * safe.  XCORR_ERR_INVALID_ARG for njobs outside 1..XCORR_NOALLOC_MAX_JOBS, null arrays or
+ * pointers, or a bad max_abs; otherwise the errors of create / set_max_abs / run. */
+#define XCORR_NOALLOC_MAX_JOBS 256
+#define XCORR_NOALLOC_SCRATCH_BYTES 41472
+int xcorr_batch_run_noalloc(int njobs, const xcorr_job *jobs, xcorr_in_dtype in_dtype, xcorr_acc_dtype acc_dtype,
+                            int max_abs, const void *const *in, void *const *out, hipStream_t stream);
+
 /* ------------------------------------------------------------------ streaming integration */
 
 /*

@@ -19,7 +19,7 @@ OBJDIR = os.path.join(HERE, "_build")
 
 SOURCES = ["xeng_mfma_i8.hip", "xeng_mfma_f16.hip", "xeng_mfma_f8.hip", "xeng_mfma_f32m.hip", "xeng_mfma_f6.hip",
            "xeng_super.hip", "xeng_chan.hip", "xeng_cmac.hip", "xeng_mfma.hip", "api.cpp", "plan.cpp", "tune.cpp",
-           "xeng_util.hip", "fengine.hip"]
+           "scratch.hip", "xeng_util.hip", "fengine.hip"]
 
 ARCH = "gfx950"
 # Packed FP32 VALU instructions are switched off for all device code.

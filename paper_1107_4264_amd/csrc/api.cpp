@@ -18,6 +18,8 @@
 
 using namespace xc;
 
+static_assert(NOALLOC_MAX_JOBS == XCORR_NOALLOC_MAX_JOBS, "header and workspace agree on the job limit");
+static_assert(NOALLOC_BYTES == XCORR_NOALLOC_SCRATCH_BYTES, "header and workspace agree on the workspace size");
 
 namespace {
 
@@ -772,6 +774,79 @@ void xcorr_batch_destroy(xcorr_batch_t *b)
     if (!b) return;
     if (b->upload_pending) (void)hipEventSynchronize(b->uploaded);
     batch_free(b);
+}
+
+int xcorr_batch_run_noalloc(int njobs, const xcorr_job *jobs, xcorr_in_dtype in_dtype, xcorr_acc_dtype acc_dtype,
+                            int max_abs, const void *const *in, void *const *out, hipStream_t stream)
+{
+    if (njobs < 1 || !jobs || !in || !out) return fail(XCORR_ERR_INVALID_ARG, "need njobs >= 1 and the job, input and output arrays");
+    if (njobs > NOALLOC_MAX_JOBS)
+        return fail(XCORR_ERR_INVALID_ARG, "xcorr_batch_run_noalloc takes at most " + std::to_string(NOALLOC_MAX_JOBS) +
+                                               " jobs (its workspace is fixed)");
+    const int in_fmt = (int)in_dtype, acc = (int)acc_dtype;
+    if (max_abs < 0) return fail(XCORR_ERR_INVALID_ARG, "max_abs must be >= 0 (0: the format's default)");
+    if (in_fmt == IN_CF32 && max_abs != 0) return fail(XCORR_ERR_INVALID_ARG, "max_abs applies to integer samples");
+    if (exact_operand_bound(acc) && in_fmt == IN_CI8 && (max_abs == 0 || max_abs > exact_operand_bound(acc)))
+        return fail(XCORR_ERR_UNSUPPORTED,
+                    "fp8 e4m3 / fp6 e3m2 need a declared max_abs <= 16 / 8 for 8-bit samples");
+    // Host planning in fixed arrays: nothing is allocated on the host or the device.
+    const int tile = batch_tile(jobs, njobs, acc);
+    const int ci = acc == ACC_F32_CMAC ? 4 : ((exact_operand_bound(acc) && in_fmt == IN_CI8) ? 4 : 8);
+    Plan plans[NOALLOC_MAX_JOBS];
+    char whole[NOALLOC_MAX_JOBS];
+    int mode = LOAD_VEC;
+    for (int j = 0; j < njobs; ++j) {
+        if (int rc = plan_batch_job(jobs[j], j, in_fmt, acc, max_abs, tile, &plans[j], &whole[j])) return rc;
+        if (!whole[j]) mode = std::max(mode, load_mode_for(plans[j].nin, in_fmt, ci));
+        if (!out[j] || (!in[j] && plans[j].ntime > 0))
+            return fail(XCORR_ERR_INVALID_ARG, "null input or output of job " + std::to_string(j));
+    }
+    void *ws = nullptr;
+    if (int e = noalloc_scratch(&ws)) return hip_fail(e, "workspace address");
+    for (int j = 0; j < njobs; ++j)
+        if (plans[j].nwindows != 1)
+            if (int rc = launch_zero(out[j], plans[j].out_bytes, stream)) return hip_fail(rc, "zero fill");
+    for (int j = 0; j < njobs; ++j)
+        if (whole[j])
+            if (int rc = launch_job(plans[j], job_from_plan(plans[j], in[j], out[j]), stream))
+                return hip_fail(rc, "whole-channel / super-tile launch of a batch job");
+    // The other jobs share one persistent launch of the tiled kernel over a work list the
+    // kernel generates from the job table (longest items first).
+    int order[NOALLOC_MAX_JOBS];
+    int ntab = 0;
+    for (int j = 0; j < njobs; ++j)
+        if (!whole[j] && plans[j].nitems > 0) order[ntab++] = j;
+    if (ntab == 0) return XCORR_OK;
+    auto item_cost = [&](int j) {
+        const double side = std::min(plans[j].nin, tile);
+        return (double)plans[j].window * side * side;
+    };
+    std::sort(order, order + ntab, [&](int a, int c) {
+        const double ca = item_cost(a), cc = item_cost(c);
+        return ca > cc || (ca == cc && a < c);
+    });
+    XJob table[NOALLOC_MAX_JOBS];
+    int64_t total = 0;
+    for (int k = 0; k < ntab; ++k) {
+        const int j = order[k];
+        XJob jb = job_from_plan(plans[j], in[j], out[j]);
+        // the launch's mode covers every job; a word-load launch keeps chunk loads per job
+        if (!(mode == LOAD_WORD && jb.load_mode == LOAD_VEC)) jb.load_mode = mode;
+        table[k] = jb;
+        total += plans[j].nitems;
+    }
+    if (int rc = launch_noalloc_setup(ws, table, ntab, stream)) return hip_fail(rc, "workspace set-up");
+    uint8_t *w = (uint8_t *)ws;
+    const XGenQueues g{(const int64_t *)(w + NOALLOC_QEND_OFF), ntab, NOALLOC_MAX_JOBS};
+    const XJob *jobs_dev = (const XJob *)(w + NOALLOC_JOBS_OFF);
+    unsigned int *counters = (unsigned int *)(w + NOALLOC_COUNTERS_OFF);
+    int nblocks = std::max(1, device_cus()) * (acc == ACC_F32_CMAC ? 4 : 2);
+    if ((int64_t)nblocks > total) nblocks = (int)total;
+    const int rc = acc == ACC_F32_CMAC
+                       ? launch_cmac_batch_gen(jobs_dev, g, counters, in_fmt, nblocks, stream)
+                       : launch_mfma_batch_gen(jobs_dev, g, counters, acc, in_fmt, tile, mode, nblocks, stream);
+    if (rc) return hip_fail(rc, "batch kernel launch");
+    return XCORR_OK;
 }
 
 }  // extern "C"

@@ -123,6 +123,26 @@ int launch_mfma_batch_gen(const XJob *jobs_dev, const XGenQueues &g, unsigned in
 int launch_cmac_batch_gen(const XJob *jobs_dev, const XGenQueues &g, unsigned int *counters_dev, int in_fmt,
                           int nblocks, hipStream_t stream);
 
+// Fixed workspace of the batch entry point that allocates nothing (one per device, for the
+// life of the process): queue counters, the generated work list's cumulative counts
+// (NQUEUE x NOALLOC_MAX_JOBS int64) and the job table (NOALLOC_MAX_JOBS XJob).
+constexpr int NOALLOC_MAX_JOBS = 256;
+constexpr size_t NOALLOC_COUNTERS_OFF = 0;
+constexpr size_t NOALLOC_QEND_OFF = 512;
+constexpr size_t NOALLOC_JOBS_OFF = NOALLOC_QEND_OFF + (size_t)NQUEUE * NOALLOC_MAX_JOBS * sizeof(int64_t);
+constexpr size_t NOALLOC_BYTES = NOALLOC_JOBS_OFF + (size_t)NOALLOC_MAX_JOBS * sizeof(XJob);
+static_assert(NQUEUE * COUNTER_STRIDE * sizeof(unsigned int) <= NOALLOC_QEND_OFF, "counters fit");
+static_assert(NOALLOC_JOBS_OFF % 16 == 0, "job table alignment");
+
+// Device address of that workspace on the current device, looked up (hipGetSymbolAddress)
+// the first time each device asks; a hipError_t as int.
+int noalloc_scratch(void **ptr);
+
+// Fill the workspace at `scratch` (a device address from noalloc_scratch) on `stream`: the
+// job table (the XJobs travel as kernel arguments, a few per launch, so nothing is read
+// from host memory after the call), then the generated queues' cumulative counts and zeroed
+// counters.  ntab <= NOALLOC_MAX_JOBS.
+int launch_noalloc_setup(void *scratch, const XJob *table, int ntab, hipStream_t stream);
 
 
 // F-engine (fengine.hip): per input and frame an nchan-point DFT of the complex 8-bit

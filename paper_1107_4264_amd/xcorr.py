@@ -100,6 +100,7 @@ def _load():
         "xcorr_batch_out_type": (c_int, [c_vp, c_int]),
         "xcorr_batch_items": (c_i64, [c_vp]),
         "xcorr_batch_destroy": (None, [c_vp]),
+        "xcorr_batch_run_noalloc": (c_int, [c_int, c_vp, c_int, c_int, c_int, c_vp, c_vp, c_vp]),
         "xcorr_stream_create": (c_vp, [c_int, c_int, c_int, c_int, c_int, c_int]),
         "xcorr_stream_set_max_abs": (c_int, [c_vp, c_int]),
         "xcorr_stream_begin": (c_int, [c_vp, c_vp, c_vp]),
@@ -307,6 +308,20 @@ def xcorr_batch_items(b):
 def xcorr_batch_destroy(b):
     _lib.xcorr_batch_destroy(b)
 
+
+def xcorr_batch_run_noalloc(jobs, in_dtype, acc_dtype, max_abs, in_ptrs, out_ptrs, stream_ptr):
+    """jobs: sequence of dicts or tuples (nstation, npol, nchan, ntime)."""
+    n = len(jobs)
+    arr = (Job * n)()
+    for k, j in enumerate(jobs):
+        if isinstance(j, dict):
+            j = (j["nstation"], j["npol"], j["nchan"], j["ntime"])
+        arr[k] = Job(*j)
+    ins = (ctypes.c_void_p * n)(*in_ptrs)
+    outs = (ctypes.c_void_p * n)(*out_ptrs)
+    return _check(_lib.xcorr_batch_run_noalloc(n, ctypes.cast(arr, ctypes.c_void_p), in_dtype, acc_dtype, max_abs,
+                                               ctypes.cast(ins, ctypes.c_void_p), ctypes.cast(outs, ctypes.c_void_p),
+                                               stream_ptr))
 
 
 def xcorr_stream_create(nstation, npol, nchan, chunk_ntime, in_dtype, acc_dtype):
