@@ -74,6 +74,7 @@ def parse():
                     help="kernel shape for the matrix-core paths: 0 automatic, 64/128 tiles, 256 whole channel")
     ap.add_argument("--no-small", action="store_true", help="skip the 64-input launch-latency figures")
     ap.add_argument("--no-ablation", action="store_true", help="skip the other kernel shapes of the workload")
+    ap.add_argument("--no-autotune", action="store_true", help="run the planner's default shapes, not the autotuned ones")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one device copy of 1 GiB (reference for HBM byte counters)")
     return ap.parse_args()
@@ -132,8 +133,15 @@ def main():
             tile = args.tile
         c = X.Correlator(ns, npol, F, T, fmt, acc, max_abs=max_abs, tile=tile or None, staging=staging or None,
                          variant=variant or None)
-        plan = X.xcorr_plan(ns, npol, F, T, in_enum, X.ACC_NAMES[acc], max_abs, c.tile)
         out = c.empty_out(dev)
+        tuned = None
+        if p in paths and acc != "f32" and not args.tile and not args.no_autotune:
+            # the paths of the workload run the shape the autotuner picks for them (every
+            # tile x staging x variant the job allows, timed on the device)
+            c.autotune(x, out, reps=5)
+            tuned = [{k: (round(v, 2) if isinstance(v, float) else v) for k, v in r.items()}
+                     for r in X.xcorr_autotune_results(c.h)]
+        plan = X.xcorr_plan(ns, npol, F, T, in_enum, X.ACC_NAMES[acc], max_abs, c.tile)
         # clocks ramp up under load: run the path untimed for a while, then the warmup steps
         t_ramp = time.perf_counter()
         while time.perf_counter() - t_ramp < args.ramp_seconds:
@@ -169,6 +177,8 @@ def main():
             "variant": c.variant,
             "launches_per_step": launches_per_step(plan),
         }
+        if tuned:
+            results[p]["autotuned_from"] = tuned
         c.close()
         outs[p] = out
         print(f"[bench] {p}: {ms:.4f} ms/step, {tflops:.1f} TFLOPS", file=sys.stderr, flush=True)
@@ -208,7 +218,8 @@ def main():
         "dtype": {"f16": "f16", "i8": "i8", "f32": "f32", "f8": "fp8", "f32m": "f32", "f6": "fp6"}[hacc],
         "data": "synthetic",
         "config": {"workload": w["name"], "nstation": ns, "npol": npol, "nchan": F, "ntime": T,
-                   "in_dtype": fmt, "max_abs": max_abs, "tile": plan["tile"],
+                   "in_dtype": fmt, "max_abs": max_abs, "tile": plan["tile"], "variant": hr["variant"],
+                   "staging": hr["staging"],
                    "path": f"{head} mfma" if hacc != "f32" else "f32 cmac"},
         "roofline": {
             "bound": "mfma" if hacc != "f32" else "alu",
@@ -266,7 +277,7 @@ def bench_fengine(args, dev):
     del v
     e = X.FEngine(ns, npol, F, T, gain)
     out = e.empty_out(dev)
-    c = X.Correlator(ns, npol, F, T, "ci8", "f16", max_abs=127)
+    c = X.Correlator(ns, npol, F, T, "ci8", "i8")
     vis = c.empty_out(dev)
     stream = torch.cuda.current_stream()
     steps = max(1, min(args.steps, 50))
@@ -295,7 +306,7 @@ def bench_fengine(args, dev):
                      "unit": "GB/s", "frac": round(nbytes / (ms_f * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)},
         "fft_tflops": round(flops / (ms_f * 1e-3) / 1e12, 3),
         "fx_chain_ms_per_pass": round(ms_fx, 5),
-        "xengine_path": "f16 mfma",
+        "xengine_path": "i8 mfma (one int32 window, ci32 output)",
     }
     print(f"[bench] F-engine: {ms_f:.4f} ms per pass, {res['hbm_gbps']} GB/s; F + X: {ms_fx:.4f} ms",
           file=sys.stderr, flush=True)

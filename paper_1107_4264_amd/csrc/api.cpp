@@ -721,8 +721,7 @@ int xcorr_batch_run(xcorr_batch_t *b, const void *const *in, void *const *out, h
     }
     for (int j = 0; j < njobs; ++j) {
         XJob jb = job_from_plan(b->plans[j], in[j], out[j]);
-        // the launch's mode covers every job; a word-load launch keeps chunk loads per job
-        if (!(b->mode == LOAD_WORD && jb.load_mode == LOAD_VEC)) jb.load_mode = b->mode;
+        jb.load_mode = b->mode;  // the launch's mode covers every job
         b->jobs_pinned[j] = jb;
     }
     if ((e = hipMemcpyAsync(b->jobs_dev, b->jobs_pinned, njobs * sizeof(XJob), hipMemcpyHostToDevice, stream)) !=
@@ -830,8 +829,7 @@ int xcorr_batch_run_noalloc(int njobs, const xcorr_job *jobs, xcorr_in_dtype in_
     for (int k = 0; k < ntab; ++k) {
         const int j = order[k];
         XJob jb = job_from_plan(plans[j], in[j], out[j]);
-        // the launch's mode covers every job; a word-load launch keeps chunk loads per job
-        if (!(mode == LOAD_WORD && jb.load_mode == LOAD_VEC)) jb.load_mode = mode;
+        jb.load_mode = mode;  // the launch's mode covers every job
         table[k] = jb;
         total += plans[j].nitems;
     }

@@ -4,12 +4,17 @@
 // samples (each component rounded half away from zero and clipped to [-127, 127]) and
 // written in the X-engine's corner-turned order [frame][channel][input] (Sec. 4.1).
 //
-// One workgroup owns one frame of a group of G inputs.  Its four waves transform one input
-// each at a time, in LDS (radix-2 decimation in time: samples stored at their bit-reversed
-// index as they arrive, then log2 F passes of butterflies with twiddles from a table the
-// workgroup fills once), and drop the requantised channels into an LDS tile [channel][G
-// inputs]; the tile leaves as rows of G consecutive inputs per channel, so the corner turn
-// costs no extra pass over HBM.  Reads are the inputs' contiguous frames.
+// One workgroup owns one frame of a group of G inputs; each of its waves transforms one
+// input at a time, independently of the others (no workgroup barrier inside a transform).
+// The transform is a Stockham autosort FFT of radix-16 passes (and one pass of radix 2, 4
+// or 8 when log2 F is not a multiple of 4): a lane gathers its R values of a pass (from the
+// input frame in memory for the first pass, from the wave's LDS buffer after that),
+// multiplies them by the pass's twiddles (a table of exp(-2 pi i m / F) the workgroup fills
+// once), does the R-point DFT in registers, and scatters the results to their sorted
+// positions.  A wave issues all its reads of a pass before its writes, so one buffer per
+// wave serves in place; the buffer and the tile rows are padded against LDS bank conflicts.  The last pass requantises and drops each channel into an LDS tile
+// [channel][G inputs], which leaves as rows of G consecutive inputs per channel: the corner
+// turn happens in LDS, and HBM sees each sample once in and once out.
 
 #include <hip/hip_runtime.h>
 
@@ -18,22 +23,65 @@
 namespace xc {
 namespace {
 
-constexpr int FE_THREADS = 256;  // four waves
-
-// Inputs per workgroup for an F-point transform: 32 (64-byte rows of the output tile) up
-// to F = 1024, fewer above so the tile stays at 64 KiB.
 template <int F>
 struct FeGeo {
-    static constexpr int G = F <= 1024 ? 32 : 32768 / F;
+    static constexpr int W = F <= 1024 ? 8 : 4;            // waves per workgroup
+    static constexpr int G = F <= 1024 ? 32 : 8;            // inputs per workgroup
+    static constexpr int THREADS = 64 * W;
     static constexpr int LOGF = __builtin_ctz(F);
-    static constexpr int WAVE_BYTES = 8 * F;               // one transform, complex fp32
-    static constexpr int TW_BYTES = 4 * F;                 // F/2 twiddles
-    static constexpr int TILE_BYTES = 2 * F * G;           // requantised [F][G] int8 pairs
-    static constexpr int LDS = 4 * WAVE_BYTES + TW_BYTES + TILE_BYTES;
+    static constexpr int WAVE_BYTES = 8 * (F + F / 16);     // one transform, complex fp32, padded
+    static constexpr int TROW = 2 * G + 16;                 // tile row bytes (padded, 16-byte aligned)
+    static constexpr int TW_BYTES = 8 * F;                  // exp(-2 pi i m / F), m < F
+    static constexpr int TILE_BYTES = TROW * F;             // requantised [F][G] int8 pairs
+    static constexpr int LDS = W * WAVE_BYTES + TW_BYTES + TILE_BYTES;
     static_assert(LDS <= 160 * 1024, "LDS budget");
+    static_assert(G % W == 0, "whole rounds");
 };
 
-__device__ __forceinline__ int bitrev(int n, int bits) { return (int)(__builtin_bitreverse32((uint32_t)n) >> (32 - bits)); }
+// exp(-2 pi i m / 16): cos and sin of 2 pi m / 16
+__device__ __forceinline__ constexpr float c16(int m)
+{
+    constexpr float c[16] = {1.0f, 0.92387953251128674f, 0.70710678118654752f, 0.38268343236508977f, 0.0f,
+                             -0.38268343236508977f, -0.70710678118654752f, -0.92387953251128674f, -1.0f,
+                             -0.92387953251128674f, -0.70710678118654752f, -0.38268343236508977f, 0.0f,
+                             0.38268343236508977f, 0.70710678118654752f, 0.92387953251128674f};
+    return c[m & 15];
+}
+__device__ __forceinline__ constexpr float s16(int m) { return c16(m + 12); }  // sin(x) = cos(x - pi/2)
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 w) { return make_float2(a.x * w.x - a.y * w.y, a.x * w.y + a.y * w.x); }
+
+constexpr int bitrev_c(int i, int bits)
+{
+    int r = 0;
+    for (int b = 0; b < bits; ++b) r |= ((i >> b) & 1) << (bits - 1 - b);
+    return r;
+}
+
+// In-register R-point DFT (R = 2, 4, 8, 16): X[k] = sum_n v[n] exp(-2 pi i k n / R), by
+// radix-2 decimation in time with compile-time twiddles.
+template <int R>
+__device__ __forceinline__ void dft_small(float2 (&v)[R])
+{
+    constexpr int LR = __builtin_ctz(R);
+    float2 t[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) t[bitrev_c(i, LR)] = v[i];
+#pragma unroll
+    for (int h = 1; h < R; h *= 2)
+#pragma unroll
+        for (int g0 = 0; g0 < R; g0 += 2 * h)
+#pragma unroll
+            for (int k = 0; k < h; ++k) {
+                const int m = k * (8 / h);  // exp(-2 pi i k / (2h)) = exp(-2 pi i m / 16)
+                const float2 w = make_float2(c16(m), -s16(m));
+                const float2 a = t[g0 + k], b = cmul(t[g0 + k + h], w);
+                t[g0 + k] = make_float2(a.x + b.x, a.y + b.y);
+                t[g0 + k + h] = make_float2(a.x - b.x, a.y - b.y);
+            }
+#pragma unroll
+    for (int i = 0; i < R; ++i) v[i] = t[i];
+}
 
 __device__ __forceinline__ int requant(float v)
 {
@@ -43,99 +91,168 @@ __device__ __forceinline__ int requant(float v)
 
 extern __shared__ __attribute__((aligned(16))) uint8_t fe_lds[];
 
+// First-pass inputs of one transform, loaded ahead (the first pass has radix 16: values
+// x[j + 16... ] of j = lane + 64 q).
+template <int F>
+struct FeFirst {
+    static constexpr int JPL = (F / 16 + 63) / 64;
+    uint32_t v[JPL][16];
+};
+
+template <int F>
+__device__ __forceinline__ void load_first(FeFirst<F> &fx, const uint16_t *src, int lane)
+{
+    constexpr int JC = F / 16;
+#pragma unroll
+    for (int q = 0; q < FeFirst<F>::JPL; ++q) {
+        const int j = lane + 64 * q;
+        if (JC % 64 != 0 && j >= JC) continue;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) fx.v[q][r] = src[j + r * JC];
+    }
+}
+
+// Position of point k in a wave's buffer: one float2 of padding after every 16, so that the
+// first pass's stores (16 consecutive points per lane) and the tile-row stores spread over
+// the LDS banks.
+__device__ __forceinline__ int pad(int k) { return k + (k >> 4); }
+
+struct FeArgs {
+    float2 *buf;          // this wave's LDS buffer
+    const float2 *tw;     // twiddle table
+    int8_t *tile;         // requantised tile [F][G]
+    float2 *spec;         // spectra output of this input and frame (stride nin), or null
+    int64_t spec_stride;
+    int g, lane;
+    float gain;
+};
+
+// One Stockham pass of radix R over a transform of F points, after NS points of output
+// sorted so far.  j = 0 .. F/R - 1: gather x[j + r F/R], twiddle by exp(-2 pi i (j mod NS)
+// r / (NS R)), R-point DFT, scatter to (j / NS) NS R + (j mod NS) + r NS.
+template <int F, int G, int R, int NS, bool LAST, bool SPECTRA>
+__device__ __forceinline__ void fft_pass(const FeArgs &a, const FeFirst<F> &fx)
+{
+    constexpr int JC = F / R, JPL = (JC + 63) / 64;
+    constexpr int TROW = 2 * G + 16;
+    float2 v[JPL][R];
+#pragma unroll
+    for (int q = 0; q < JPL; ++q) {
+        const int j = a.lane + 64 * q;
+        if (JC % 64 != 0 && j >= JC) continue;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if constexpr (NS == 1) {
+                const uint32_t w = fx.v[q][r];
+                v[q][r] = make_float2((float)(int8_t)(w & 0xFF), (float)(int8_t)(w >> 8));
+            } else {
+                v[q][r] = a.buf[pad(j + r * JC)];
+            }
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int q = 0; q < JPL; ++q) {
+        const int j = a.lane + 64 * q;
+        if (JC % 64 != 0 && j >= JC) continue;
+        const int jm = NS == 1 ? 0 : (j & (NS - 1));
+        if constexpr (NS > 1) {
+#pragma unroll
+            for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], a.tw[(jm * r * (F / (NS * R))) & (F - 1)]);
+        }
+        dft_small<R>(v[q]);
+        const int d0 = (j / NS) * NS * R + jm;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int k = d0 + r * NS;
+            if constexpr (!LAST) {
+                a.buf[pad(k)] = v[q][r];
+            } else if constexpr (SPECTRA) {
+                a.spec[(int64_t)k * a.spec_stride] = make_float2(a.gain * v[q][r].x, a.gain * v[q][r].y);
+            } else {
+                const uint32_t p =
+                    (uint32_t)(requant(a.gain * v[q][r].x) & 0xFF) | ((uint32_t)(requant(a.gain * v[q][r].y) & 0xFF) << 8);
+                *(uint16_t *)(a.tile + k * TROW + 2 * a.g) = (uint16_t)p;
+            }
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+}
+
+// The passes of an F-point transform: radix 16 while at least four bits remain, then one
+// pass of radix 2^REM.
+template <int F, int G, int NS, int REM, bool SPECTRA>
+__device__ __forceinline__ void fft_passes(const FeArgs &a, const FeFirst<F> &fx)
+{
+    constexpr int LR = REM >= 4 ? 4 : REM;
+    constexpr bool LAST = REM <= 4;
+    static_assert(NS > 1 || LR == 4, "the first pass has radix 16");
+    fft_pass<F, G, (1 << LR), NS, LAST, SPECTRA>(a, fx);
+    if constexpr (!LAST) fft_passes<F, G, NS * (1 << LR), REM - LR, SPECTRA>(a, fx);
+}
+
 // SPECTRA: write the scaled spectra as complex fp32 [frame][channel][input] instead of the
 // requantised samples (no tile; for checking the transform itself).
 template <int F, bool SPECTRA>
-__global__ __launch_bounds__(FE_THREADS) void fengine_kernel(const int8_t *__restrict__ in, void *__restrict__ out,
-                                                             int nin, int64_t nsamp, int nframes, float gain)
+__global__ __launch_bounds__(FeGeo<F>::THREADS) void fengine_kernel(const int8_t *__restrict__ in, void *__restrict__ out,
+                                                                    int nin, int64_t nsamp, int nframes, float gain)
 {
     using Ge = FeGeo<F>;
-    constexpr int G = Ge::G;
+    constexpr int G = Ge::G, W = Ge::W;
     const int ngroups = (nin + G - 1) / G;
     const int t = (int)(blockIdx.x / ngroups);
     const int i0 = (int)(blockIdx.x % ngroups) * G;
     if (t >= nframes) return;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    float2 *tw = (float2 *)(fe_lds + 4 * Ge::WAVE_BYTES);
-    float2 *buf = (float2 *)(fe_lds + wave * Ge::WAVE_BYTES);
-    int8_t *tile = (int8_t *)(fe_lds + 4 * Ge::WAVE_BYTES + Ge::TW_BYTES);
+    float2 *tw = (float2 *)(fe_lds + W * Ge::WAVE_BYTES);
+    int8_t *tile = (int8_t *)(fe_lds + W * Ge::WAVE_BYTES + Ge::TW_BYTES);
 
-    // twiddles exp(-2 pi i k / F), k < F/2 (sincospi of an exact multiple of 2/F)
-    for (int k = threadIdx.x; k < F / 2; k += FE_THREADS) {
+    // twiddles exp(-2 pi i m / F) (sincospi of an exact multiple of 2/F)
+    for (int m = threadIdx.x; m < F; m += Ge::THREADS) {
         float s, c;
-        sincospif(-2.0f * (float)k / (float)F, &s, &c);
-        tw[k] = make_float2(c, s);
+        sincospif(-2.0f * (float)m / (float)F, &s, &c);
+        tw[m] = make_float2(c, s);
     }
     __syncthreads();
 
     const int nin_here = min(G, nin - i0);
-    // every wave runs the same number of rounds (barriers inside the transform)
-    for (int r = 0; r < (G + 3) / 4; ++r) {
-        const int g = 4 * r + wave;
-        const bool have = g < nin_here;
-        if (have) {
-            // frame t of input i0 + g: F samples, two per lane and load
-            const int16_t *src = (const int16_t *)in + ((int64_t)(i0 + g) * nsamp + (int64_t)t * F);
-            for (int n = 2 * lane; n < F; n += 128) {
-                const uint32_t w = *(const uint32_t *)(src + n);
-                const float r0 = (float)(int8_t)(w & 0xFF), m0 = (float)(int8_t)((w >> 8) & 0xFF);
-                const float r1 = (float)(int8_t)((w >> 16) & 0xFF), m1 = (float)(int8_t)(w >> 24);
-                buf[bitrev(n, Ge::LOGF)] = make_float2(r0, m0);
-                buf[bitrev(n + 1, Ge::LOGF)] = make_float2(r1, m1);
-            }
-        }
-        __syncthreads();
-#pragma unroll 1
-        for (int s = 0; s < Ge::LOGF; ++s) {
-            const int half = 1 << s;
-            if (have) {
-                for (int b = lane; b < F / 2; b += 64) {
-                    const int pos = b & (half - 1);
-                    const int i = ((b >> s) << (s + 1)) + pos, j = i + half;
-                    const float2 w = tw[pos << (Ge::LOGF - 1 - s)];
-                    const float2 u = buf[i], v = buf[j];
-                    const float2 vw = make_float2(v.x * w.x - v.y * w.y, v.x * w.y + v.y * w.x);
-                    buf[i] = make_float2(u.x + vw.x, u.y + vw.y);
-                    buf[j] = make_float2(u.x - vw.x, u.y - vw.y);
-                }
-            }
-            __syncthreads();
-        }
-        if (have) {
-            if constexpr (SPECTRA) {
-                float2 *o = (float2 *)out;
-                for (int k = lane; k < F; k += 64) {
-                    const float2 v = buf[k];
-                    o[((int64_t)t * F + k) * nin + i0 + g] = make_float2(gain * v.x, gain * v.y);
-                }
-            } else {
-                for (int k = lane; k < F; k += 64) {
-                    const float2 v = buf[k];
-                    const uint32_t q = (uint32_t)(requant(gain * v.x) & 0xFF) | ((uint32_t)(requant(gain * v.y) & 0xFF) << 8);
-                    *(uint16_t *)(tile + 2 * (k * G + g)) = (uint16_t)q;
-                }
-            }
-        }
-        __syncthreads();
+    FeArgs a;
+    a.buf = (float2 *)(fe_lds + wave * Ge::WAVE_BYTES);
+    a.tw = tw;
+    a.tile = tile;
+    a.lane = lane;
+    a.gain = gain;
+    a.spec_stride = nin;
+    // the next input's frame is loaded while the current one is transformed
+    auto frame = [&](int g) { return (const uint16_t *)in + ((int64_t)(i0 + g) * nsamp + (int64_t)t * F); };
+    auto transform = [&](int g, const FeFirst<F> &fx) __attribute__((always_inline)) {
+        a.g = g;
+        a.spec = SPECTRA ? (float2 *)out + ((int64_t)t * F * nin + i0 + g) : nullptr;
+        fft_passes<F, G, 1, Ge::LOGF, SPECTRA>(a, fx);
+    };
+    FeFirst<F> fx0, fx1;  // two named buffers (an indexed pair would live in scratch memory)
+    if (wave < nin_here) load_first<F>(fx0, frame(wave), lane);
+    for (int g = wave; g < nin_here; g += 2 * W) {
+        if (g + W < nin_here) load_first<F>(fx1, frame(g + W), lane);
+        transform(g, fx0);
+        if (g + W >= nin_here) break;
+        if (g + 2 * W < nin_here) load_first<F>(fx0, frame(g + 2 * W), lane);
+        transform(g + W, fx1);
     }
     if constexpr (!SPECTRA) {
-        // tile rows -> out[t][k][i0 .. i0 + nin_here): 4-byte pieces (two inputs)
-        int8_t *o = (int8_t *)out;
-        constexpr int PIECES = G / 2;
-        for (int e = threadIdx.x; e < F * PIECES; e += FE_THREADS) {
-            const int k = e / PIECES, pc = e - k * PIECES;
-            const int g = 2 * pc;
-            int8_t *dst = o + 2 * (((int64_t)t * F + k) * nin + i0 + g);
-            const uint32_t v = *(const uint32_t *)(tile + 2 * (k * G + g));
-            if (g + 1 < nin_here) {
-                if ((((uintptr_t)dst) & 3) == 0) {
-                    *(uint32_t *)dst = v;
-                } else {
-                    *(uint16_t *)dst = (uint16_t)v;
-                    *(uint16_t *)(dst + 2) = (uint16_t)(v >> 16);
-                }
-            } else if (g < nin_here) {
-                *(uint16_t *)dst = (uint16_t)v;
+        __syncthreads();
+        // tile rows -> out[t][k][i0 .. i0 + nin_here)
+        int8_t *o = (int8_t *)out + 2 * ((int64_t)t * F * nin + i0);
+        if (nin_here == G && nin % 8 == 0 && ((uintptr_t)out & 15) == 0) {
+            constexpr int PIECES = G / 8;  // 16 bytes = 8 inputs
+            for (int e = threadIdx.x; e < F * PIECES; e += Ge::THREADS) {
+                const int k = e / PIECES, pc = e - k * PIECES;
+                *(uint4 *)(o + 2 * ((int64_t)k * nin + 8 * pc)) = *(const uint4 *)(tile + k * Ge::TROW + 16 * pc);
+            }
+        } else {
+            for (int e = threadIdx.x; e < F * G; e += Ge::THREADS) {
+                const int k = e / G, g = e - k * G;
+                if (g < nin_here) *(uint16_t *)(o + 2 * ((int64_t)k * nin + g)) = *(const uint16_t *)(tile + k * Ge::TROW + 2 * g);
             }
         }
     }
@@ -150,8 +267,8 @@ int launch_f(const int8_t *in, void *out, int nin, int64_t nsamp, int nframes, f
     const int64_t blocks = ngroups * nframes;
     if (blocks <= 0) return 0;
     if (blocks > 0x7FFFFFFF) return (int)hipErrorInvalidValue;
-    hipLaunchKernelGGL((fengine_kernel<F, SPECTRA>), dim3((unsigned)blocks), dim3(FE_THREADS), LDS, stream, in, out,
-                       nin, nsamp, nframes, gain);
+    hipLaunchKernelGGL((fengine_kernel<F, SPECTRA>), dim3((unsigned)blocks), dim3(FeGeo<F>::THREADS), LDS, stream, in,
+                       out, nin, nsamp, nframes, gain);
     return (int)hipGetLastError();
 }
 

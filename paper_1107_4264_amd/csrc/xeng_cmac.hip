@@ -233,7 +233,8 @@ __global__ __launch_bounds__(NTHREADS) void xeng_cmac_batch_kernel(const XJob *j
             __syncthreads();
             if (it >= q.end[qq]) break;
             const XItem item = items[it];
-            process_item<IN>(jobs[item.job], item.chan, item.tile, item.window, lds);
+            const XJob jb = jobs[item.job];  // a register copy (see the tiled batch kernel)
+            process_item<IN>(jb, item.chan, item.tile, item.window, lds);
         }
     }
 }
@@ -254,7 +255,8 @@ __global__ __launch_bounds__(NTHREADS) void xeng_cmac_batch_gen_kernel(const XJo
             __syncthreads();
             XItem item;
             if (!gen_item(jobs, gq, qq, it, item)) break;
-            process_item<IN>(jobs[item.job], item.chan, item.tile, item.window, lds);
+            const XJob jb = jobs[item.job];  // a register copy (see the tiled batch kernel)
+            process_item<IN>(jb, item.chan, item.tile, item.window, lds);
         }
     }
 }

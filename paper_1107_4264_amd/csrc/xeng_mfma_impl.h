@@ -67,9 +67,10 @@ struct Op<ACC_F32M> {
     static constexpr int G = 4, WORDS = 8, TB = 16;
     using acc_t = f32x16;
 };
-// fp6 e3m2: 32x32x64 MFMAs like fp8, the 32 values of a lane packed into six words.  The
-// unit holds the plain operand (words 0..5, 6..7 zero) and the rotated one (-im, re) for
-// the imaginary product (words 8..13): staged once, read as the column operand.
+// fp6 e3m2: 32x32x64 MFMAs like fp8, the 32 values of a lane packed into six words (one
+// packed conversion from fp16).  The unit holds the plain operand (words 0..5, 6..7 zero)
+// and the rotated one (-im, re) for the imaginary product (words 8..13): staged once, read
+// as the column operand.
 template <>
 struct Op<ACC_F6> {
     static constexpr int G = 16, WORDS = 16, TB = 32;
@@ -245,30 +246,19 @@ __device__ __forceinline__ void load_rows(__amdgpu_buffer_rsrc_t rs, uint32_t ro
     }
 }
 
-// fp6 e3m2 bit pattern (sign bit 5, three exponent bits of bias 3, two mantissa bits) of an
-// integer v with |v| <= 8, exactly: the magnitudes 1..8 are 1.0 x 2^0, 1.0 x 2^1, 1.5 x 2^1,
-// 1.0 x 2^2, 1.25 x 2^2, 1.5 x 2^2, 1.75 x 2^2 and 1.0 x 2^3.
-__device__ __forceinline__ uint32_t e3m2_bits(int v)
+// 16 words of (re, im) fp16 pairs -> the 32 values as fp6 e3m2 in six words (words 6, 7
+// zero), by gfx950's packed conversion (scale 1).  Exact for integers of [-8, 8].
+__device__ __forceinline__ void pack_fp6(const uint32_t (&h)[16], uint32_t *w)
 {
-    const uint32_t a = (uint32_t)(v < 0 ? -v : v);
-    const uint32_t lo = 0x12100C00u;  // codes of 0, 1, 2, 3 (byte k)
-    const uint32_t hi = 0x17161514u;  // codes of 4, 5, 6, 7
-    const uint32_t c = a >= 8 ? 0x18u : (((a < 4 ? lo : hi) >> (8 * (a & 3))) & 0xFFu);
-    return c | (v < 0 ? 0x20u : 0u);
-}
-
-// 32 six-bit codes -> six words, value k at bits 6k .. 6k + 5 of the 192-bit operand; words
-// 6 and 7 zero.
-__device__ __forceinline__ void pack_fp6(const uint32_t (&c)[32], uint32_t *w)
-{
+    typedef _Float16 h32 __attribute__((ext_vector_type(32)));
+    typedef uint32_t u32x16 __attribute__((ext_vector_type(16)));
+    u32x16 hv;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) w[k] = 0;
+    for (int k = 0; k < 16; ++k) hv[k] = h[k];
+    const auto p = __builtin_amdgcn_cvt_scalef32_pk32_bf6_f16(__builtin_bit_cast(h32, hv), 1.0f);
 #pragma unroll
-    for (int k = 0; k < 32; ++k) {
-        const int bit = 6 * k, word = bit >> 5, sh = bit & 31;
-        w[word] |= c[k] << sh;
-        if (sh > 26) w[word + 1] |= c[k] >> (32 - sh);
-    }
+    for (int k = 0; k < 6; ++k) w[k] = p[k];
+    w[6] = w[7] = 0;
 }
 
 // Convert units E0 .. E1-1 (inputs of the chunk) of a task's rows to operand units and
@@ -321,19 +311,19 @@ __device__ __forceinline__ void stage_store(uint8_t *lds, int buf, int side, int
                     u[m] = f16_bits(re) | (f16_bits(im) << 16);
                 }
             } else if constexpr (ACC == ACC_F6) {
-                // 32 values (re, im of 16 rows) as e3m2 codes, and the rotated (-im, re)
-                uint32_t c[32], r[32];
+                // the 16 rows' (re, im) as fp16 pairs, packed to fp6; then the rotated
+                // (-im, re) pairs likewise
+                uint32_t h[16];
 #pragma unroll
                 for (int m = 0; m < 16; ++m) {
                     int re, im;
                     pair_of<IN>(rows[m], e, re, im);
-                    c[2 * m] = e3m2_bits(re);
-                    c[2 * m + 1] = e3m2_bits(im);
-                    r[2 * m] = c[2 * m + 1] ^ 0x20u;
-                    r[2 * m + 1] = c[2 * m];
+                    h[m] = f16_bits(re) | (f16_bits(im) << 16);
                 }
-                pack_fp6(c, u);
-                pack_fp6(r, u + 8);
+                pack_fp6(h, u);
+#pragma unroll
+                for (int m = 0; m < 16; ++m) h[m] = rotate_pairs<ACC_F16>(h[m]);
+                pack_fp6(h, u + 8);
             } else if constexpr (ACC == ACC_F32M) {
                 // plane 0: real parts of the four rows, plane 1: imaginary parts
 #pragma unroll
@@ -748,18 +738,17 @@ __device__ __forceinline__ void unit_from_samples(const uint32_t (&s)[G], Frag<W
             o.w[4 + m] = __builtin_bit_cast(uint32_t, (float)im);
         }
     } else if constexpr (ACC == ACC_F6) {
-        uint32_t c[32], r[32];
+        uint32_t h[16];
 #pragma unroll
         for (int m = 0; m < 16; ++m) {
             int re, im;
             pr(m, re, im);
-            c[2 * m] = e3m2_bits(re);
-            c[2 * m + 1] = e3m2_bits(im);
-            r[2 * m] = c[2 * m + 1] ^ 0x20u;
-            r[2 * m + 1] = c[2 * m];
+            h[m] = f16_bits(re) | (f16_bits(im) << 16);
         }
-        pack_fp6(c, o.w);
-        pack_fp6(r, o.w + 8);
+        pack_fp6(h, o.w);
+#pragma unroll
+        for (int m = 0; m < 16; ++m) h[m] = rotate_pairs<ACC_F16>(h[m]);
+        pack_fp6(h, o.w + 8);
     } else {
 #pragma unroll
         for (int m = 0; m < 8; ++m) {
@@ -936,17 +925,14 @@ __global__ __launch_bounds__(NTHREADS, 2) void xeng_cache_kernel(XJob p)
     process_item_cache<ACC, IN, TILE>(p, f, g, w);
 }
 
-// One work item of a batch launch.  A word-load launch still runs the jobs whose rows allow
-// 16-byte chunks with them.
+// One work item of a batch launch, in the launch's load mode (the narrowest any of its jobs
+// needs; a word-load launch still loads whole chunks with single wide loads where a row
+// allows it, so jobs with chunk-aligned rows lose nothing, and a single mode keeps one copy
+// of the item code in the kernel: two would not fit the register file).
 template <int ACC, int IN, int TILE, int MODE>
 __device__ __forceinline__ void run_batch_item(const XJob &jb, const XItem &item, uint8_t *lds)
 {
-    if constexpr (MODE == LOAD_WORD) {
-        if (jb.load_mode == LOAD_VEC) process_item<ACC, IN, TILE, LOAD_VEC>(jb, item.chan, item.tile, item.window, lds);
-        else process_item<ACC, IN, TILE, LOAD_WORD>(jb, item.chan, item.tile, item.window, lds);
-    } else {
-        process_item<ACC, IN, TILE, MODE>(jb, item.chan, item.tile, item.window, lds);
-    }
+    process_item<ACC, IN, TILE, MODE>(jb, item.chan, item.tile, item.window, lds);
 }
 
 // Persistent batched kernel: workgroups take (job, channel, tile, window) items off the
@@ -967,7 +953,10 @@ __global__ __launch_bounds__(NTHREADS, 2) void xeng_mfma_batch_kernel(const XJob
             __syncthreads();
             if (it >= q.end[qq]) break;
             const XItem item = items[it];
-            run_batch_item<ACC, IN, TILE, MODE>(jobs[item.job], item, lds);
+            // a copy in registers: through a reference every field would be re-read after
+            // each store the compiler cannot tell apart from the job table
+            const XJob jb = jobs[item.job];
+            run_batch_item<ACC, IN, TILE, MODE>(jb, item, lds);
         }
     }
 }
@@ -990,7 +979,10 @@ __global__ __launch_bounds__(NTHREADS, 2) void xeng_mfma_batch_gen_kernel(const 
             __syncthreads();
             XItem item;
             if (!gen_item(jobs, gq, qq, it, item)) break;
-            run_batch_item<ACC, IN, TILE, MODE>(jobs[item.job], item, lds);
+            // a copy in registers: through a reference every field would be re-read after
+            // each store the compiler cannot tell apart from the job table
+            const XJob jb = jobs[item.job];
+            run_batch_item<ACC, IN, TILE, MODE>(jb, item, lds);
         }
     }
 }
