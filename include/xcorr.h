@@ -108,7 +108,9 @@ enum {
     XCORR_ERR_UNSUPPORTED = -2, /* combination that would not be exact */
     XCORR_ERR_OOM = -3,         /* device or host allocation failed */
     XCORR_ERR_HIP = -4,         /* a HIP runtime call failed (see xcorr_last_error) */
-    XCORR_ERR_RANGE = -5        /* a size exceeds what the library indexes */
+    XCORR_ERR_RANGE = -5        /* a size exceeds what the library indexes, or (with
+                                   validation on) a sample component is outside the declared
+                                   range */
 };
 
 /* ------------------------------------------------------------------ one correlation job */
@@ -213,6 +215,22 @@ void xcorr_autotune_clear(void);
  * xcorr_out_bytes) on `stream` (0 = the null stream).  The device the handle was created on
  * must be current (XCORR_ERR_INVALID_ARG otherwise). */
 int xcorr_run(xcorr_handle_t *h, const void *in, void *out, hipStream_t stream);
+
+/* Range check of integer samples (the exactness conditions of Sec. 2.3: every window and
+ * every operand type is sized for components bounded by max_abs; on the int8 path a
+ * component of -128 would overflow when the imaginary product negates it).  Counts the
+ * real and imaginary components of `in` (device, xcorr_in_bytes bytes, any alignment)
+ * outside [-max_abs, max_abs] (the declared bound, else the format's default: 127 for CI8 on
+ * the int8 path, so -128 counts) and writes the count to *nbad (host).  One pass over the
+ * input on `stream`, then waits for the stream: not allowed while the stream is capturing a
+ * graph (XCORR_ERR_UNSUPPORTED).  The first call allocates an 8-byte device counter, which
+ * xcorr_destroy frees.  CF32 input: *nbad = 0. */
+int xcorr_validate(xcorr_handle_t *h, const void *in, hipStream_t stream, int64_t *nbad);
+
+/* on = 1: every xcorr_run first runs xcorr_validate and, if any component is out of range,
+ * returns XCORR_ERR_RANGE without computing (out untouched); such runs wait for the stream
+ * and cannot be captured.  on = 0 (the default): no check. */
+int xcorr_set_validation(xcorr_handle_t *h, int on);
 
 void xcorr_destroy(xcorr_handle_t *h);
 

@@ -200,6 +200,12 @@ struct xcorr_handle {
     Plan plan;
     int device;
     std::vector<TuneVal> tuned;  // every shape the last xcorr_autotune timed
+    bool validate = false;                  // xcorr_run checks the sample range first
+    unsigned long long *range_dev = nullptr;  // count of the range check (8 bytes, on first use)
+    ~xcorr_handle()
+    {
+        if (range_dev) (void)hipFree(range_dev);
+    }
 };
 
 extern "C" {
@@ -488,11 +494,57 @@ int xcorr_get_tile(const xcorr_handle_t *h)
     return h->plan.tile;
 }
 
+int xcorr_validate(xcorr_handle_t *h, const void *in, hipStream_t stream, int64_t *nbad)
+{
+    if (!h || !nbad) return fail(XCORR_ERR_INVALID_ARG, "null handle or count");
+    const Plan &p = h->plan;
+    if (!in && p.in_bytes > 0) return fail(XCORR_ERR_INVALID_ARG, "null input");
+    if (int rc = check_device(h->device)) return rc;
+    *nbad = 0;
+    if (p.in_fmt == IN_CF32 || p.in_bytes == 0) return XCORR_OK;
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    hipError_t e = hipStreamIsCapturing(stream, &cap);
+    if (e != hipSuccess) return hip_fail((int)e, "capture status");
+    if (cap != hipStreamCaptureStatusNone)
+        return fail(XCORR_ERR_UNSUPPORTED, "the range check waits for its result: not inside a graph capture");
+    if (!h->range_dev) {
+        e = hipMalloc((void **)&h->range_dev, sizeof(unsigned long long));
+        if (e != hipSuccess) {
+            h->range_dev = nullptr;
+            return fail(XCORR_ERR_OOM, "range-check counter");
+        }
+    }
+    if (int rc = launch_range_count(in, p.in_bytes, p.in_fmt == IN_CI4, p.max_abs, h->range_dev, stream))
+        return hip_fail(rc, "range check");
+    unsigned long long n = 0;
+    e = hipMemcpyAsync(&n, h->range_dev, sizeof n, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail((int)e, "range-check result");
+    *nbad = (int64_t)n;
+    return XCORR_OK;
+}
+
+int xcorr_set_validation(xcorr_handle_t *h, int on)
+{
+    if (!h) return fail(XCORR_ERR_INVALID_ARG, "null handle");
+    if (on != 0 && on != 1) return fail(XCORR_ERR_INVALID_ARG, "validation is 0 (off) or 1 (on)");
+    h->validate = on == 1;
+    return XCORR_OK;
+}
+
 int xcorr_run(xcorr_handle_t *h, const void *in, void *out, hipStream_t stream)
 {
     if (!h) return fail(XCORR_ERR_INVALID_ARG, "null handle");
     if (!out || (!in && h->plan.ntime > 0)) return fail(XCORR_ERR_INVALID_ARG, "null input or output");
     if (int rc = check_device(h->device)) return rc;
+    if (h->validate) {
+        int64_t nbad = 0;
+        if (int rc = xcorr_validate(h, in, stream, &nbad)) return rc;
+        if (nbad)
+            return fail(XCORR_ERR_RANGE, std::to_string(nbad) + " sample components outside [-" +
+                                             std::to_string(h->plan.max_abs) + ", " +
+                                             std::to_string(h->plan.max_abs) + "]: nothing computed");
+    }
     return enqueue_job(h->plan, in, out, stream);
 }
 
@@ -512,7 +564,8 @@ int xcorr_out_type(const xcorr_handle_t *h)
 
 struct xcorr_batch {
     int device = 0;
-    int in_fmt = 0, acc = 0, tile = 0, mode = 0, nblocks = 0;
+    int in_fmt = 0, acc = 0, tile = 0, mode = 0;
+    int cus = 0;
     std::vector<xcorr_job> jobs;
     std::vector<Plan> plans;
     std::vector<char> whole;  // job runs the whole-channel kernel (its own persistent launch)
@@ -648,9 +701,7 @@ int batch_plan(xcorr_batch *b, int max_abs)
     b->mode = mode;
     b->queues = qs;
     b->nitems = (int64_t)items.size();
-    const int cus = device_cus();
-    b->nblocks = std::max(1, cus) * (b->acc == ACC_F32_CMAC ? 4 : 2);
-    if ((int64_t)b->nblocks > b->nitems) b->nblocks = (int)std::max<int64_t>(1, b->nitems);
+    b->cus = std::max(1, device_cus());
     return XCORR_OK;
 }
 
@@ -742,10 +793,13 @@ int xcorr_batch_run(xcorr_batch_t *b, const void *const *in, void *const *out, h
             if (rc) return hip_fail(rc, "whole-channel / super-tile launch of a batch job");
         }
     if (b->nitems == 0) return XCORR_OK;
+    // persistent workgroups: as many as fit the compute units at once
+    int64_t nblocks = (int64_t)b->cus * (b->acc == ACC_F32_CMAC ? 4 : 2);
+    nblocks = std::max<int64_t>(1, std::min(nblocks, b->nitems));
     rc = b->acc == ACC_F32_CMAC
-             ? launch_cmac_batch(b->jobs_dev, b->items_dev, b->queues, b->counters_dev, b->in_fmt, b->nblocks, stream)
+             ? launch_cmac_batch(b->jobs_dev, b->items_dev, b->queues, b->counters_dev, b->in_fmt, (int)nblocks, stream)
              : launch_mfma_batch(b->jobs_dev, b->items_dev, b->queues, b->counters_dev, b->acc, b->in_fmt, b->tile,
-                                 b->mode, b->nblocks, stream);
+                                 b->mode, (int)nblocks, stream);
     if (rc) return hip_fail(rc, "batch kernel launch");
     return XCORR_OK;
 }

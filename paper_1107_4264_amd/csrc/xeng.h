@@ -60,6 +60,10 @@ int launch_mfma(const XJob &job, int acc, int in_fmt, hipStream_t stream);
 int launch_mfma_cache(const XJob &job, int acc, int in_fmt, hipStream_t stream);
 int launch_cmac(const XJob &job, int in_fmt, hipStream_t stream);
 int launch_zero(void *ptr, size_t bytes, hipStream_t stream);
+// Zero *count, then add the number of sample components of `in` (bytes of CI8, or of CI4
+// when ci4) outside [-max_abs, max_abs] to it.
+int launch_range_count(const void *in, size_t bytes, bool ci4, int max_abs, unsigned long long *count,
+                       hipStream_t stream);
 // Whole-channel kernel (tile 256): persistent, job.grid workgroups of 512 threads walk the
 // job.nitems (channel, window) items, window-major.
 int launch_chan(const XJob &job, int acc, hipStream_t stream);

@@ -83,6 +83,8 @@ def _load():
         "xcorr_autotune_load": (c_int, [ctypes.c_char_p]),
         "xcorr_autotune_clear": (None, []),
         "xcorr_run": (c_int, [c_vp, c_vp, c_vp, c_vp]),
+        "xcorr_validate": (c_int, [c_vp, c_vp, c_vp, ctypes.POINTER(c_i64)]),
+        "xcorr_set_validation": (c_int, [c_vp, c_int]),
         "xcorr_destroy": (None, [c_vp]),
         "xcorr_in_bytes": (c_sz, [c_vp]),
         "xcorr_out_bytes": (c_sz, [c_vp]),
@@ -229,6 +231,16 @@ def xcorr_autotune_clear():
 
 def xcorr_run(h, in_ptr, out_ptr, stream_ptr):
     return _check(_lib.xcorr_run(h, in_ptr, out_ptr, stream_ptr))
+
+
+def xcorr_validate(h, in_ptr, stream_ptr):
+    n = ctypes.c_int64(0)
+    _check(_lib.xcorr_validate(h, in_ptr, stream_ptr, ctypes.byref(n)))
+    return int(n.value)
+
+
+def xcorr_set_validation(h, on):
+    return _check(_lib.xcorr_set_validation(h, int(on)))
 
 
 def xcorr_destroy(h):
@@ -432,7 +444,7 @@ class Correlator:
     ('ci8', 'ci4', 'cf32' / 'f32', 'i8', 'f16', 'f8')."""
 
     def __init__(self, nstation, npol, nchan, ntime, in_dtype="ci8", acc="f16", max_abs=None, tile=None,
-                 window=None, staging=None, variant=None):
+                 window=None, staging=None, variant=None, validate=False):
         self.nstation, self.npol, self.nchan, self.ntime = nstation, npol, nchan, ntime
         self.in_dtype = IN_NAMES.get(in_dtype, in_dtype)
         self.acc = ACC_NAMES.get(acc, acc)
@@ -447,6 +459,8 @@ class Correlator:
             xcorr_set_tile(self.h, int(tile))
         if variant is not None:
             xcorr_set_variant(self.h, int(variant))
+        if validate:
+            xcorr_set_validation(self.h, 1)
 
     @property
     def tile(self):
@@ -494,6 +508,13 @@ class Correlator:
         return xcorr_autotune(self.h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                               _stream_ptr(stream), reps)
 
+    def count_out_of_range(self, x, stream=None):
+        """Number of sample components of x outside [-max_abs, max_abs] (waits for the
+        stream)."""
+        if not x.is_cuda or x.numel() * x.element_size() != xcorr_in_bytes(self.h):
+            raise ValueError("input must be a device tensor of the plan's size")
+        return xcorr_validate(self.h, ctypes.c_void_p(x.data_ptr()), _stream_ptr(stream))
+
     def run(self, x, out=None, stream=None):
         """x: device tensor holding xcorr_in_bytes bytes of samples; returns the output."""
         if not x.is_cuda:
@@ -519,6 +540,7 @@ class Batch:
         self.b = xcorr_batch_create(self.jobs, self.in_dtype, self.acc)
         if max_abs is not None:
             xcorr_batch_set_max_abs(self.b, int(max_abs))
+
 
     def close(self):
         if self.b:
