@@ -65,7 +65,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--ramp-seconds", type=float, default=0.3,
                     help="untimed run time per path before the warmup steps, so that clocks have settled")
-    ap.add_argument("--workload", default="n256-ci8", choices=sorted(WORKLOADS) + ["batch64", "stream", "fengine"])
+    ap.add_argument("--workload", default="n256-ci8", choices=sorted(WORKLOADS) + ["batch64", "stream", "stream-full", "fengine"])
     ap.add_argument("--paths", default=None, help="comma-separated paths (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
@@ -96,8 +96,8 @@ def main():
     dev = torch.device("cuda:0")
     if args.workload == "batch64":
         return bench_batch(args, dev)
-    if args.workload == "stream":
-        return bench_stream(args, dev)
+    if args.workload in ("stream", "stream-full"):
+        return bench_stream(args, dev, STREAM if args.workload == "stream" else STREAM_FULL)
     if args.workload == "fengine":
         print(json.dumps(bench_fengine(args, dev)), flush=True)
         return
@@ -527,8 +527,15 @@ STREAM = {
     "dist": ("gauss", 20.0, 127), "seed_index": 4, "path": "i8",
 }
 
+# The same integration at its full size: 4096 channels, 34.4 GB per chunk (two pinned host
+# chunks of 2^35 bytes, 549.8 GB copied per integration).
+STREAM_FULL = dict(STREAM, nchan=4096,
+                   name="streaming integration: 1024 inputs (512 stations x 2 pol), 4096 channels, 16 chunks of 4096 "
+                        "samples (65536 samples) from a pool of 2 pinned host chunks, ci8 gaussian sigma=20 clipped "
+                        "to +-127")
 
-def bench_stream(args, dev):
+
+def bench_stream(args, dev, w):
     """End-to-end chunked integration from pinned host memory (copies overlapped with the
     X-engine); a step is the whole integration, wall time includes the host-to-device copies."""
     import numpy as np
@@ -537,12 +544,12 @@ def bench_stream(args, dev):
     from paper_1107_4264_amd import synth
     from paper_1107_4264_amd import xcorr as X
 
-    w = STREAM
     ns, npol, F, C = w["nstation"], w["npol"], w["nchan"], w["chunk"]
     nin = ns * npol
     seed = synth.SEED_BASE + w["seed_index"]
     pool = []
     for k in range(w["pool"]):
+        print(f"[bench] generating pinned chunk {k} ({C}x{F}x{nin} ci8)", file=sys.stderr, flush=True)
         d = synth.voltages_torch(seed, C, F, nin, w["dist"], dev, t0=k * C)
         h = torch.empty(d.shape, dtype=torch.int8, pin_memory=True)
         h.copy_(d)
@@ -563,9 +570,11 @@ def bench_stream(args, dev):
     steps = max(1, min(args.steps, 3))
     integrate()
     torch.cuda.synchronize()
+    print("[bench] warm-up integration done", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    for _ in range(steps):
+    for k in range(steps):
         integrate()
+        print(f"[bench] integration {k} issued", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) / steps
     # the X-engine alone on one resident chunk, for the overlap figure
