@@ -166,8 +166,9 @@ int xcorr_get_staging(const xcorr_handle_t *h);
  * kernel build): whole-channel kernel (tile 256) 0..3 — bit 0 keeps one time block fewer in
  * the LDS copy ring (int8: 3 instead of 4 blocks of 64 samples; fp16: 4 instead of 5 of
  * 32), bit 1 swaps which of the two waves sharing a SIMD takes the five-block work list;
- * super-tiles (tile 512) 0..1 — bit 0 uses a three-block instead of a four-block ring; the
- * other kernels have variant 0 only.  XCORR_ERR_INVALID_ARG outside that range.  Same
+ * super-tiles (tile 512) 0..3 — bit 0 uses a three-block instead of a four-block ring, bit 1
+ * stages the rectangles' column operands also in rotated (-im, re) form, so that no wave
+ * rotates a fragment; the other kernels have variant 0 only.  XCORR_ERR_INVALID_ARG outside that range.  Same
  * visibilities for every variant. */
 int xcorr_set_variant(xcorr_handle_t *h, int variant);
 int xcorr_get_variant(const xcorr_handle_t *h);

@@ -384,7 +384,8 @@ __device__ __forceinline__ i32x4s block_rsrc(const XJob &p, const Cursor<TB> &c,
 //   waves 4..7: the off-diagonal 2x2 squares rows {4,5} / {6,7} x columns {0,1} / {2,3}.
 // F: block rows of the fragments a wave reads; BR/BC: per block, the fragment (index into
 // F) of its rows and of its columns; ROT: fragments also needed in rotated form, the
-// columns, or with ROWROT the rows (waves 1 and 3 have two row and four column fragments).
+// columns, or with ROWROT the rows (waves 1 and 3 have two row and four column fragments);
+// PRE: the rotated column operands are read from LDS (fragments RC) instead.
 // PAIR: blocks b whose right neighbour (same block row, next block column) is block b + 1,
 // stored together; SINGLE: the block without a neighbour (-1: none).
 template <int W>
@@ -394,7 +395,7 @@ struct Spec<0> {
     static constexpr int NF = 3, NB = 5;
     static constexpr int F[4] = {0, 1, 2, 0}, BR[5] = {0, 1, 1, 2, 2}, BC[5] = {0, 0, 1, 0, 1};
     static constexpr bool ROT[4] = {true, true, false, false};
-    static constexpr bool ROWROT = false;
+    static constexpr bool ROWROT = false, PRE = false;
     static constexpr int NPAIR = 2, PAIR[2] = {1, 3}, SINGLE = 0;
 };
 template <>
@@ -402,7 +403,7 @@ struct Spec<1> {
     static constexpr int NF = 4, NB = 5;
     static constexpr int F[4] = {2, 3, 0, 1}, BR[5] = {0, 1, 1, 1, 1}, BC[5] = {0, 0, 1, 2, 3};
     static constexpr bool ROT[4] = {true, true, false, false};
-    static constexpr bool ROWROT = true;
+    static constexpr bool ROWROT = true, PRE = false;
     static constexpr int NPAIR = 2, PAIR[2] = {3, 1}, SINGLE = 0;
 };
 template <>
@@ -410,7 +411,7 @@ struct Spec<2> {
     static constexpr int NF = 3, NB = 5;
     static constexpr int F[4] = {4, 5, 6, 0}, BR[5] = {0, 1, 1, 2, 2}, BC[5] = {0, 0, 1, 0, 1};
     static constexpr bool ROT[4] = {true, true, false, false};
-    static constexpr bool ROWROT = false;
+    static constexpr bool ROWROT = false, PRE = false;
     static constexpr int NPAIR = 2, PAIR[2] = {1, 3}, SINGLE = 0;
 };
 template <>
@@ -418,7 +419,7 @@ struct Spec<3> {
     static constexpr int NF = 4, NB = 5;
     static constexpr int F[4] = {6, 7, 4, 5}, BR[5] = {0, 1, 1, 1, 1}, BC[5] = {0, 0, 1, 2, 3};
     static constexpr bool ROT[4] = {true, true, false, false};
-    static constexpr bool ROWROT = true;
+    static constexpr bool ROWROT = true, PRE = false;
     static constexpr int NPAIR = 2, PAIR[2] = {3, 1}, SINGLE = 0;
 };
 template <int I, int J>
@@ -426,7 +427,7 @@ struct SquareSpec {
     static constexpr int NF = 4, NB = 4;
     static constexpr int F[4] = {2 * I, 2 * I + 1, 2 * J, 2 * J + 1}, BR[5] = {0, 0, 1, 1, 0}, BC[5] = {2, 3, 2, 3, 0};
     static constexpr bool ROT[4] = {false, false, true, true};
-    static constexpr bool ROWROT = false;
+    static constexpr bool ROWROT = false, PRE = false;
     static constexpr int NPAIR = 2, PAIR[2] = {0, 2}, SINGLE = -1;
 };
 template <>
@@ -476,6 +477,22 @@ template <int ACC, typename S, typename Early, typename Mid>
 __device__ __forceinline__ void mma_step(const Frag<COp<ACC>::FW> (&A)[S::NF], AccSet<ACC> &acc, Early &&early,
                                          Mid &&mid)
 {
+    if constexpr (S::PRE) {
+        // rotated column operands staged in LDS: no rotation in registers
+        static_for<S::NB>([&](auto B) __attribute__((always_inline)) {
+            constexpr int b = decltype(B)::value;
+            mma(acc.re[b], A[S::BR[b]], A[S::BC[b]]);
+            if constexpr (b == 0) early();
+            __builtin_amdgcn_sched_barrier(0);
+        });
+        static_for<S::NB>([&](auto B) __attribute__((always_inline)) {
+            constexpr int b = decltype(B)::value;
+            mma(acc.im[b], A[S::BR[b]], A[S::RC[b]]);
+            if constexpr (b == 1) mid();
+            __builtin_amdgcn_sched_barrier(0);
+        });
+        return;
+    }
     constexpr int NROT = rot_count<S>();
     static_assert(NROT <= S::NB, "rotations ride on the real-part MFMAs");
     Frag<COp<ACC>::FW> Rt[S::NF];

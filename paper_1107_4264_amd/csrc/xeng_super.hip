@@ -17,7 +17,10 @@
 //     floor((2^31 - 1) / (128 m^2)) samples);
 //   * fp8: e4m3 pairs (all of -8..7 are exact), with the usual fp32 windows.
 // The K-steps (software pipelined, Sec. 4.4's staging re-planned for gfx950), rotations and
-// stores are those of the whole-channel kernel.
+// stores are those of the whole-channel kernel.  Variant bit 1 (rectangles): the widening
+// also writes the column segment rotated to (-im, re) pairs, so that the imaginary
+// products read their column operand from LDS: each column fragment is rotated once per
+// block instead of once per K-step by each of the four waves that read it.
 
 #include "xeng_chan_dev.h"
 
@@ -25,21 +28,25 @@ namespace xc {
 namespace {
 
 constexpr int SP_TB = 32;                  // time rows per block
-constexpr int SP_CROW = 768;               // widened bytes per time row (384 inputs)
-constexpr int SP_CONV = SP_TB * SP_CROW;   // widened bytes per block
 
 // Raw geometry per sample format: BPS bytes per sample; AROW / BROW raw bytes per time row
 // of the row / column segment; NA / NB copy instructions (1 KiB each) per block for them;
 // DPW copies per wave per block (NA / 8 row copies and one column copy, the column copies
 // repeated by two waves when NB = 4); UB raw bytes of one 16-byte widened chunk.
-// Variant V (chosen by the autotuner): bit 0 keeps one block fewer in the raw ring.
-template <int IN, int V = 0>
+// Variant V (chosen by the autotuner): bit 0 keeps one block fewer in the raw ring; bit 1
+// (rectangles, PRE) adds the rotated column segment to the widened rows.  CROW: widened
+// bytes per time row (256 row inputs, 128 column inputs, with PRE their rotated copy);
+// CONV: widened bytes per block.
+template <int IN, int V = 0, int TRI = 1>
 struct SGeo {
     static constexpr int BPS = IN == IN_CI8 ? 2 : 1;
     static constexpr int AROW = 256 * BPS, BROW = 128 * BPS;
     static constexpr int RAW = SP_TB * (AROW + BROW);
     static constexpr int RING = 4 - (V & 1);  // measured: 4 slots beat 3, 5, 6 and 8 (4-bit, 1024 inputs)
-    static constexpr int LDS = RING * RAW + 2 * SP_CONV;
+    static constexpr bool PRE = TRI == 0 && (V & 2);
+    static constexpr int CROW = PRE ? 1024 : 768;
+    static constexpr int CONV = SP_TB * CROW;
+    static constexpr int LDS = RING * RAW + 2 * CONV;
     static constexpr int NA = SP_TB * AROW / 1024, NB = SP_TB * BROW / 1024;
     static constexpr int DPW = NA / 8 + 1;
     static constexpr int UB = 8 * BPS;
@@ -50,6 +57,19 @@ struct SGeo {
 // {2 (W%2), 2 (W%2) + 1} of the column segment, stored as fragment rows 8..11.
 template <int W>
 struct RectSpec : SquareSpec<(W >> 1), 4 + (W & 1)> {};
+
+// The same with the rotated column operands read from LDS: fragment rows 12..15 hold the
+// column segment's block rows 0..3 as (-im, re) pairs.
+template <int W>
+struct RectRotSpec {
+    static constexpr int I = W >> 1, J = W & 1;
+    static constexpr int NF = 6, NB = 4;
+    static constexpr int F[6] = {2 * I, 2 * I + 1, 8 + 2 * J, 9 + 2 * J, 12 + 2 * J, 13 + 2 * J};
+    static constexpr int BR[5] = {0, 0, 1, 1, 0}, BC[5] = {2, 3, 2, 3, 0}, RC[5] = {4, 5, 4, 5, 0};
+    static constexpr bool ROT[6] = {false, false, false, false, false, false};
+    static constexpr bool ROWROT = false, PRE = true;
+    static constexpr int NPAIR = 2, PAIR[2] = {0, 2}, SINGLE = -1;
+};
 
 // Position in the work of a workgroup: item g = step * grid + pos, pos = (b % 8) grid / 8 +
 // b / 8 when the grid is a multiple of 8 (consecutive items on one XCD); item
@@ -161,6 +181,33 @@ __device__ __forceinline__ void ci4x4_to_i8x8(uint32_t w, uint32_t &lo, uint32_t
     hi = __builtin_amdgcn_perm(im, re, 0x07030602u);
 }
 
+// -x of each byte (two's complement, no carries between bytes; -(-128) stays -128, which
+// no operand here reaches)
+__device__ __forceinline__ uint32_t neg_bytes(uint32_t x)
+{
+    const uint32_t n = ~x;
+    return ((n & 0x7F7F7F7Fu) + 0x01010101u) ^ (n & 0x80808080u);
+}
+
+// The rotated forms, (-im, re) pairs, of ci4x4_to_i8x8 and ci4x4_to_e4m3x8.
+__device__ __forceinline__ void ci4x4_to_i8x8_rot(uint32_t w, uint32_t &lo, uint32_t &hi)
+{
+    const uint32_t t = w & 0xF0F0F0F0u;
+    const uint32_t re = (t >> 1) | (t & 0x80808080u);
+    const uint32_t u = (w << 4) & 0xF0F0F0F0u;
+    const uint32_t nim = neg_bytes((u >> 1) | (u & 0x80808080u));
+    lo = __builtin_amdgcn_perm(re, nim, 0x05010400u);
+    hi = __builtin_amdgcn_perm(re, nim, 0x07030602u);
+}
+
+__device__ __forceinline__ void ci4x4_to_e4m3x8_rot(uint32_t w, uint32_t &lo, uint32_t &hi)
+{
+    const uint32_t re = nibbles_to_e4m3((w >> 4) & 0x0F0F0F0Fu);
+    const uint32_t nim = nibbles_to_e4m3(w & 0x0F0F0F0Fu) ^ 0x80808080u;
+    lo = __builtin_amdgcn_perm(re, nim, 0x05010400u);
+    hi = __builtin_amdgcn_perm(re, nim, 0x07030602u);
+}
+
 // int8 from 4-bit samples: the operands are 8 x the samples, the sums 64 x the
 // visibilities (exact shift)
 template <int ACC, int IN, typename S>
@@ -180,14 +227,18 @@ __device__ __forceinline__ void descale_store(const XJob &p, int f, int lane, Ac
 template <int ACC, int IN, int TRI, int W, int V>
 __device__ __forceinline__ void run_wave_super(const XJob &p, int lane)
 {
-    using Gs = SGeo<IN, V>;
+    using Gs = SGeo<IN, V, TRI>;
     constexpr int RING = Gs::RING, DPW = Gs::DPW, NKS = SP_TB / COp<ACC>::KS;
     constexpr int NAW = Gs::NA / 8;    // row-segment copies per wave per block
     static_assert(NKS >= 1 && SP_TB % COp<ACC>::KS == 0, "whole K-steps per block");
     using acc_t = typename COp<ACC>::acc_t;
-    using S = typename std::conditional<TRI != 0, Spec<W>, RectSpec<W>>::type;
-    constexpr int NU = TRI ? 2 : 3;    // widening instructions per wave per block
-    constexpr int NCH = TRI ? 32 : 48; // 16-byte chunks of a widened row
+    constexpr bool PRE = Gs::PRE;
+    constexpr int CROW_W = Gs::CROW, CONV = Gs::CONV;
+    using S = typename std::conditional<TRI != 0, Spec<W>,
+                                        typename std::conditional<PRE, RectRotSpec<W>, RectSpec<W>>::type>::type;
+    constexpr int NUP = TRI ? 2 : 3;    // plain widening instructions per wave per block
+    constexpr int NU = NUP + (PRE ? 1 : 0);  // and one of rotated column chunks with PRE
+    constexpr int NCH = TRI ? 32 : 48;  // 16-byte chunks of a plain widened row
     const uint64_t row_stride = (uint64_t)p.nchan * p.nin * Gs::BPS;
     const uint32_t lds0 = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) uint8_t *)chan_lds;
     const uint32_t conv0 = lds0 + RING * Gs::RAW;
@@ -215,31 +266,50 @@ __device__ __forceinline__ void run_wave_super(const XJob &p, int lane)
                   voff_b);
     };
 
-    // widening units: instruction m < NU of wave W covers unit U = 512 m + 64 W + lane, row
-    // U / NCH, chunk U % NCH (chunks 0..31 from segment A, 32..47 from segment B)
-    static_assert(NU * 512 == SP_TB * NCH, "units cover the block");
+    // widening units: instruction m < NUP of wave W covers unit U = 512 m + 64 W + lane, row
+    // U / NCH, chunk U % NCH (chunks 0..31 from segment A, 32..47 from segment B); with PRE,
+    // instruction NUP covers rotated unit U = 64 W + lane, row U / 16, chunk 48 + U % 16
+    // from chunk U % 16 of segment B
+    static_assert(NUP * 512 == SP_TB * NCH && (!PRE || 512 == SP_TB * 16), "units cover the block");
     uint32_t usrc[NU], udst[NU];
 #pragma unroll
-    for (int m = 0; m < NU; ++m) {
+    for (int m = 0; m < NUP; ++m) {
         const int U = 512 * m + 64 * W + lane;
         const int row = U / NCH, c = U - NCH * (U / NCH);
         usrc[m] = (uint32_t)(c < 32 ? row * Gs::AROW + Gs::UB * c
                                     : SP_TB * Gs::AROW + row * Gs::BROW + Gs::UB * (c - 32));
-        udst[m] = (uint32_t)(row * SP_CROW + 16 * (c ^ (4 * (row & 3))));
+        udst[m] = (uint32_t)(row * CROW_W + 16 * (c ^ (4 * (row & 3))));
+    }
+    if constexpr (PRE) {
+        const int U = 64 * W + lane;
+        const int row = U >> 4, r = U & 15, c = 48 + r;
+        usrc[NUP] = (uint32_t)(SP_TB * Gs::AROW + row * Gs::BROW + Gs::UB * r);
+        udst[NUP] = (uint32_t)(row * CROW_W + 16 * (c ^ (4 * (row & 3))));
     }
     typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
     typedef __attribute__((address_space(3))) u32x2 lds_u2;
     // raw unit: 8 bytes of 4-bit samples, or 16 bytes of 8-bit samples (already int8 pairs)
     using raw_t = typename std::conditional<IN == IN_CI8, u32x4, u32x2>::type;
-    auto widen = [&](raw_t v, uint32_t dst) __attribute__((always_inline)) {
+    auto widen = [&](raw_t v, uint32_t dst, auto RotTag) __attribute__((always_inline)) {
+        constexpr bool ROTU = decltype(RotTag)::value;
         if constexpr (IN == IN_CI8) {
             static_assert(ACC == ACC_I8, "8-bit samples: int8 path only");
-            *(lds_u4 *)(uintptr_t)dst = v;
+            if constexpr (ROTU)
+                *(lds_u4 *)(uintptr_t)dst = (u32x4){rotate_pairs<ACC_I8>(v[0]), rotate_pairs<ACC_I8>(v[1]),
+                                                    rotate_pairs<ACC_I8>(v[2]), rotate_pairs<ACC_I8>(v[3])};
+            else
+                *(lds_u4 *)(uintptr_t)dst = v;
         } else {
             uint32_t o0, o1, o2, o3;
-            if constexpr (ACC == ACC_I8) {
+            if constexpr (ACC == ACC_I8 && ROTU) {
+                ci4x4_to_i8x8_rot(v[0], o0, o1);
+                ci4x4_to_i8x8_rot(v[1], o2, o3);
+            } else if constexpr (ACC == ACC_I8) {
                 ci4x4_to_i8x8(v[0], o0, o1);
                 ci4x4_to_i8x8(v[1], o2, o3);
+            } else if constexpr (ROTU) {
+                ci4x4_to_e4m3x8_rot(v[0], o0, o1);
+                ci4x4_to_e4m3x8_rot(v[1], o2, o3);
             } else {
                 ci4x4_to_e4m3x8(v[0], o0, o1);
                 ci4x4_to_e4m3x8(v[1], o2, o3);
@@ -253,13 +323,15 @@ __device__ __forceinline__ void run_wave_super(const XJob &p, int lane)
     };
     // the whole widening of one block (prologue)
     auto widen_block = [&](uint32_t src, uint32_t dst) __attribute__((always_inline)) {
-#pragma unroll
-        for (int m = 0; m < NU; ++m) widen(raw_read(src + usrc[m]), dst + udst[m]);
+        static_for<NU>([&](auto M) __attribute__((always_inline)) {
+            constexpr int m = decltype(M)::value;
+            widen(raw_read(src + usrc[m]), dst + udst[m], std::integral_constant<bool, (m >= NUP)>{});
+        });
     };
 
     uint32_t lb[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) lb[q] = conv0 + lane_base<ACC, SP_CROW>(lane, q);
+    for (int q = 0; q < 4; ++q) lb[q] = conv0 + lane_base<ACC, CROW_W>(lane, q);
 
     AccSet<ACC> acc;
 #pragma unroll
@@ -294,10 +366,10 @@ __device__ __forceinline__ void run_wave_super(const XJob &p, int lane)
         const int dslot = slot == 0 ? RING - 1 : slot - 1;
         dc.next(p);
         const uint32_t csrc = lds0 + (slot == RING - 1 ? 0 : slot + 1) * Gs::RAW;
-        const uint32_t cdst = conv0 + (fb ^ 1) * SP_CONV;
+        const uint32_t cdst = conv0 + (fb ^ 1) * CONV;
         uint32_t lv[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) lv[q] = lb[q] + fb * SP_CONV;
+        for (int q = 0; q < 4; ++q) lv[q] = lb[q] + fb * CONV;
         // K-step k issues copy m (of the block RING - 1 ahead) when m NKS / DPW == k, and
         // widens unit u of the next block when u NKS / NU == k: the unit is read before the
         // MFMAs, widened and stored between them
@@ -316,10 +388,11 @@ __device__ __forceinline__ void run_wave_super(const XJob &p, int lane)
         auto mid = [&](auto K) __attribute__((always_inline)) {
             static_for<NU>([&](auto U) __attribute__((always_inline)) {
                 constexpr int u = decltype(U)::value;
-                if constexpr (u * NKS / NU == decltype(K)::value) widen(rr[u], cdst + udst[u]);
+                if constexpr (u * NKS / NU == decltype(K)::value)
+                    widen(rr[u], cdst + udst[u], std::integral_constant<bool, (u >= NUP)>{});
             });
         };
-        block_raw<ACC, S, NKS, SP_CROW>(lv, acc, copy, mid, pre);
+        block_raw<ACC, S, NKS, CROW_W>(lv, acc, copy, mid, pre);
         slot = slot == RING - 1 ? 0 : slot + 1;
         fb ^= 1;
         nc.next(p);
@@ -360,7 +433,7 @@ __global__ __launch_bounds__(CT, 1) void xeng_super_kernel(XJob p)
 template <int ACC, int IN, int TRI, int V>
 int launch_super_kind(XJob job, int cus, hipStream_t stream)
 {
-    constexpr int LDS = SGeo<IN, V>::LDS;
+    constexpr int LDS = SGeo<IN, V, TRI>::LDS;
     if (int e = allow_lds_on_device<xeng_super_kernel<ACC, IN, TRI, V>>(LDS)) return e;
     const int ns = job.ntile_side;
     job.nitems = (int64_t)job.nwindows * job.nchan * (TRI ? ns : ns * (ns - 1));
@@ -370,16 +443,26 @@ int launch_super_kind(XJob job, int cus, hipStream_t stream)
     return (int)hipGetLastError();
 }
 
+// Variant bit 0 applies to both launches, bit 1 (staged rotated column operands) to the
+// rectangles.
 template <int ACC, int IN>
 int launch_super_pair(const XJob &job, int cus, hipStream_t stream)
 {
-    if (job.variant == 1) {
-        if (int e = launch_super_kind<ACC, IN, 1, 1>(job, cus, stream)) return e;
-        return launch_super_kind<ACC, IN, 0, 1>(job, cus, stream);
+    int e;
+    switch (job.variant) {
+    case 0: e = launch_super_kind<ACC, IN, 1, 0>(job, cus, stream); break;
+    case 1: e = launch_super_kind<ACC, IN, 1, 1>(job, cus, stream); break;
+    case 2: e = launch_super_kind<ACC, IN, 1, 0>(job, cus, stream); break;
+    case 3: e = launch_super_kind<ACC, IN, 1, 1>(job, cus, stream); break;
+    default: return (int)hipErrorInvalidValue;
     }
-    if (job.variant != 0) return (int)hipErrorInvalidValue;
-    if (int e = launch_super_kind<ACC, IN, 1, 0>(job, cus, stream)) return e;
-    return launch_super_kind<ACC, IN, 0, 0>(job, cus, stream);
+    if (e) return e;
+    switch (job.variant) {
+    case 0: return launch_super_kind<ACC, IN, 0, 0>(job, cus, stream);
+    case 1: return launch_super_kind<ACC, IN, 0, 1>(job, cus, stream);
+    case 2: return launch_super_kind<ACC, IN, 0, 2>(job, cus, stream);
+    default: return launch_super_kind<ACC, IN, 0, 3>(job, cus, stream);
+    }
 }
 
 }  // namespace

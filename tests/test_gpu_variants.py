@@ -2,7 +2,8 @@
 for bit: the tiled kernel without its LDS stage (operands loaded per wave through the L1 /
 L2 caches, the hardware-managed cache of Sec. 4.3) on every matrix-core path, the
 compile-time variants of the whole-channel kernel (ring depth, wave order) and of the
-super-tiles (ring depth), and the fp32 matrix-core path."""
+super-tiles (ring depth, rotated column operands staged in LDS), and the fp32
+matrix-core path."""
 
 from __future__ import annotations
 
@@ -106,16 +107,21 @@ def test_chan_variants(oracle_mod, acc, variant, shape):
     _check(got, oracle_mod.xcorr(x, ns, npol), f"chan-variant/{acc}/{variant}/{shape}")
 
 
+@pytest.mark.parametrize("variant", [1, 2, 3])
 @pytest.mark.parametrize("fmt_acc", [("ci4", "i8"), ("ci4", "f8"), ("ci8", "i8")], ids=lambda t: "-".join(t))
-@pytest.mark.parametrize("shape", [(256, 2, 2, 100), (200, 2, 2, 37)], ids=lambda s: "x".join(map(str, s)))
-def test_super_variant(oracle_mod, fmt_acc, shape):
+@pytest.mark.parametrize("shape", [(256, 2, 2, 100), (200, 2, 2, 37), (136, 2, 3, 70)],
+                         ids=lambda s: "x".join(map(str, s)))
+def test_super_variant(oracle_mod, fmt_acc, shape, variant):
+    """Ring depth (bit 0) and rotated column operands staged in LDS (bit 1): 512 inputs (two
+    full super-rows), 400 and 272 (a partial last super-row, its rotated chunks past the
+    last input zero)."""
     fmt, acc = fmt_acc
     ns, npol, F, T = shape
     v = synth.voltages_np(5300 + ns, T, F, ns * npol, ("uniform", -8, 7) if fmt == "ci4" else ("gauss", 40.0, 127))
     x = synth.pack_ci4(v) if fmt == "ci4" else v
-    say("super variant", fmt, acc, shape)
-    got, sh = _run(x, ns, npol, fmt, acc, tile=512, variant=1)
-    assert sh == (512, 0, 1)
+    say("super variant", fmt, acc, shape, variant)
+    got, sh = _run(x, ns, npol, fmt, acc, tile=512, variant=variant)
+    assert sh == (512, 0, variant)
     want = oracle_mod.xcorr(x, ns, npol, fmt=oracle_mod.CI4 if fmt == "ci4" else oracle_mod.CI8)
     _check(got, want, f"super-variant/{fmt}/{acc}/{shape}")
 

@@ -57,8 +57,8 @@ def test_load_lookup_save_roundtrip(tmp_path):
     LINE.format(arch="gfx950", ns=128, fc=2, tc=4, fmt=0, acc=2, ma=18, tile=96, st=0, var=0, us=1.0),
     # staging through the caches only on 64 / 128 tiles
     LINE.format(arch="gfx950", ns=128, fc=2, tc=4, fmt=0, acc=2, ma=18, tile=256, st=1, var=0, us=1.0),
-    # super-tiles have two variants
-    LINE.format(arch="gfx950", ns=512, fc=2, tc=4, fmt=1, acc=1, ma=8, tile=512, st=0, var=2, us=1.0),
+    # super-tiles have four variants
+    LINE.format(arch="gfx950", ns=512, fc=2, tc=4, fmt=1, acc=1, ma=8, tile=512, st=0, var=4, us=1.0),
     # the old format without an architecture
     '{"nstation": 128, "npol": 2, "nchan": 4, "ntime": 10, "in": 0, "acc": 2, "max_abs": 18, "tile": 128, "us": 1.0}\n',
     "not json\n",
