@@ -305,6 +305,9 @@ def bench_fengine(args, dev):
         "roofline": {"bound": "hbm", "achieved": round(nbytes / (ms_f * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(nbytes / (ms_f * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)},
         "fft_tflops": round(flops / (ms_f * 1e-3) / 1e12, 3),
+        # the transform's 5 F log2 F flops against the fp32 vector peak: the kernel issues
+        # several vector instructions per flop (conversions, requantisation, LDS addressing)
+        "fft_frac_of_fp32_vector_peak": round(flops / (ms_f * 1e-3) / 1e12 / PEAK_TFLOPS["f32"], 4),
         "fx_chain_ms_per_pass": round(ms_fx, 5),
         "xengine_path": "i8 mfma (one int32 window, ci32 output)",
     }

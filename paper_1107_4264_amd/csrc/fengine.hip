@@ -18,6 +18,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <utility>
+
 #include "xeng.h"
 
 namespace xc {
@@ -51,36 +53,101 @@ __device__ __forceinline__ constexpr float s16(int m) { return c16(m + 12); }  /
 
 __device__ __forceinline__ float2 cmul(float2 a, float2 w) { return make_float2(a.x * w.x - a.y * w.y, a.x * w.y + a.y * w.x); }
 
-constexpr int bitrev_c(int i, int bits)
+// Calls fn(std::integral_constant<int, i>) for i = 0 .. N-1 (compile-time indices).
+template <typename Fn, int... I>
+__device__ __forceinline__ void sfor_impl(Fn &&fn, std::integer_sequence<int, I...>)
 {
-    int r = 0;
-    for (int b = 0; b < bits; ++b) r |= ((i >> b) & 1) << (bits - 1 - b);
-    return r;
+    (fn(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename Fn>
+__device__ __forceinline__ void sfor(Fn &&fn)
+{
+    sfor_impl(fn, std::make_integer_sequence<int, N>{});
 }
 
-// In-register R-point DFT (R = 2, 4, 8, 16): X[k] = sum_n v[n] exp(-2 pi i k n / R), by
-// radix-2 decimation in time with compile-time twiddles.
+// a * exp(-2 pi i M / 16) for a compile-time M: multiples of pi/2 are exchanges and sign
+// changes, odd multiples of pi/4 one shared scale, the rest a complex product.
+template <int M>
+__device__ __forceinline__ float2 w16(float2 a)
+{
+    constexpr int m = M & 15;
+    constexpr float H = 0.70710678118654752f;
+    if constexpr (m == 0) return a;
+    else if constexpr (m == 4) return make_float2(a.y, -a.x);
+    else if constexpr (m == 8) return make_float2(-a.x, -a.y);
+    else if constexpr (m == 12) return make_float2(-a.y, a.x);
+    else if constexpr (m == 2) return make_float2(H * (a.x + a.y), H * (a.y - a.x));
+    else if constexpr (m == 6) return make_float2(H * (a.y - a.x), -H * (a.x + a.y));
+    else if constexpr (m == 10) return make_float2(-H * (a.x + a.y), H * (a.x - a.y));
+    else if constexpr (m == 14) return make_float2(H * (a.x - a.y), H * (a.x + a.y));
+    else {
+        constexpr float c = c16(m), sn = s16(m);
+        return make_float2(a.x * c + a.y * sn, a.y * c - a.x * sn);
+    }
+}
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+
+// 4-point DFT in place, natural order in and out.
+__device__ __forceinline__ void dft4(float2 &a0, float2 &a1, float2 &a2, float2 &a3)
+{
+    const float2 t0 = cadd(a0, a2), t1 = csub(a0, a2), t2 = cadd(a1, a3), t3 = csub(a1, a3);
+    a0 = cadd(t0, t2);
+    a2 = csub(t0, t2);
+    a1 = make_float2(t1.x + t3.y, t1.y - t3.x);  // t1 - i t3
+    a3 = make_float2(t1.x - t3.y, t1.y + t3.x);  // t1 + i t3
+}
+
+// In-register R-point DFT (R = 2, 4, 8, 16), X[k] = sum_n v[n] exp(-2 pi i k n / R), natural
+// order in and out: 8 = 2 x 4 and 16 = 4 x 4 (Cooley-Tukey, decimation in time) with the
+// twiddles between the stages at compile time.
 template <int R>
 __device__ __forceinline__ void dft_small(float2 (&v)[R])
 {
-    constexpr int LR = __builtin_ctz(R);
-    float2 t[R];
-#pragma unroll
-    for (int i = 0; i < R; ++i) t[bitrev_c(i, LR)] = v[i];
-#pragma unroll
-    for (int h = 1; h < R; h *= 2)
-#pragma unroll
-        for (int g0 = 0; g0 < R; g0 += 2 * h)
-#pragma unroll
-            for (int k = 0; k < h; ++k) {
-                const int m = k * (8 / h);  // exp(-2 pi i k / (2h)) = exp(-2 pi i m / 16)
-                const float2 w = make_float2(c16(m), -s16(m));
-                const float2 a = t[g0 + k], b = cmul(t[g0 + k + h], w);
-                t[g0 + k] = make_float2(a.x + b.x, a.y + b.y);
-                t[g0 + k + h] = make_float2(a.x - b.x, a.y - b.y);
-            }
-#pragma unroll
-    for (int i = 0; i < R; ++i) v[i] = t[i];
+    if constexpr (R == 2) {
+        const float2 t = v[0];
+        v[0] = cadd(t, v[1]);
+        v[1] = csub(t, v[1]);
+    } else if constexpr (R == 4) {
+        dft4(v[0], v[1], v[2], v[3]);
+    } else if constexpr (R == 8) {
+        float2 e[4] = {v[0], v[2], v[4], v[6]}, o[4] = {v[1], v[3], v[5], v[7]};
+        dft4(e[0], e[1], e[2], e[3]);
+        dft4(o[0], o[1], o[2], o[3]);
+        sfor<4>([&](auto K) __attribute__((always_inline)) {
+            constexpr int k = decltype(K)::value;
+            const float2 t = w16<2 * k>(o[k]);  // exp(-2 pi i k / 8)
+            v[k] = cadd(e[k], t);
+            v[k + 4] = csub(e[k], t);
+        });
+    } else {
+        static_assert(R == 16, "radix 2, 4, 8 or 16");
+        // n = 4 n1 + n2, k = k1 + 4 k2: 4-point DFTs over n1, twiddles exp(-2 pi i n2 k1 / 16),
+        // 4-point DFTs over n2
+        float2 y[4][4];
+        sfor<4>([&](auto N2) __attribute__((always_inline)) {
+            constexpr int n2 = decltype(N2)::value;
+            y[n2][0] = v[n2];
+            y[n2][1] = v[4 + n2];
+            y[n2][2] = v[8 + n2];
+            y[n2][3] = v[12 + n2];
+            dft4(y[n2][0], y[n2][1], y[n2][2], y[n2][3]);
+            sfor<4>([&](auto K1) __attribute__((always_inline)) {
+                constexpr int k1 = decltype(K1)::value;
+                y[n2][k1] = w16<n2 * k1>(y[n2][k1]);
+            });
+        });
+        sfor<4>([&](auto K1) __attribute__((always_inline)) {
+            constexpr int k1 = decltype(K1)::value;
+            float2 b0 = y[0][k1], b1 = y[1][k1], b2 = y[2][k1], b3 = y[3][k1];
+            dft4(b0, b1, b2, b3);
+            v[k1] = b0;
+            v[k1 + 4] = b1;
+            v[k1 + 8] = b2;
+            v[k1 + 12] = b3;
+        });
+    }
 }
 
 __device__ __forceinline__ int requant(float v)
