@@ -150,14 +150,15 @@ __device__ __forceinline__ i32x4s seg_rsrc(const XJob &p, const C &c, int first,
 // (8 re, 8 im) int8 pairs.
 // e4m3 codes of four signed 4-bit values (one per byte, low nibble): two 8-entry byte
 // tables (values 0..7 and -8..-1, indexed by the low three bits) and the sign bit of each
-// nibble spread to a byte mask ((t << 8) - t is 0xFF per byte where t is 1, no carries).
+// nibble spread to a byte mask by a third byte permute (selector byte 0 or 1 picks 0x00 or
+// 0xFF; the arithmetic form (t << 8) - t is folded into a quarter-rate multiply).
 __device__ __forceinline__ uint32_t nibbles_to_e4m3(uint32_t n)
 {
     const uint32_t idx = n & 0x07070707u;
     const uint32_t pos = __builtin_amdgcn_perm(0x4E4C4A48u, 0x44403800u, idx);  // 0, 1, .., 7
     const uint32_t neg = __builtin_amdgcn_perm(0xB8C0C4C8u, 0xCACCCED0u, idx);  // -8, -7, .., -1
     const uint32_t t = (n >> 3) & 0x01010101u;
-    const uint32_t m = (t << 8) - t;
+    const uint32_t m = __builtin_amdgcn_perm(0u, 0x0000FF00u, t);
     return (neg & m) | (pos & ~m);
 }
 
