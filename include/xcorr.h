@@ -184,8 +184,9 @@ int xcorr_set_window(xcorr_handle_t *h, int window);
 
 /* Autotuner (the parameter search of Sec. 4.3 / 4.4 and 6, done on the device): run every
  * kernel shape the job allows — tile (xcorr_set_tile) x staging (xcorr_set_staging) x
- * kernel variant (xcorr_set_variant) — `reps` times (after one warm-up) on `in` / `out` on
- * `stream`, timed with HIP events, keep the fastest on the handle and record it in the
+ * kernel variant (xcorr_set_variant) — `reps` times (after one warm-up; before the first
+ * shape, `reps` untimed runs bring the clocks up) on `in` / `out` on `stream`, timed with
+ * HIP events, keep the fastest on the handle and record it in the
  * process-wide tuning cache under the job's class: the current device's architecture
  * (e.g. "gfx950"), nstation, npol, formats, max_abs, requested window, and the power-of-two
  * buckets ceil(log2(nchan)) and ceil(log2(ntime)).  Handles created or re-planned later
