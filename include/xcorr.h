@@ -142,7 +142,8 @@ int xcorr_set_max_abs(xcorr_handle_t *h, int max_abs);
  *        256 x 128 rectangles, each held by one persistent workgroup (two launches); needs
  *        CI4 input on the int8 or fp8 path, or CI8 input on the int8 path, and nin a
  *        multiple of 16 in 272..2048; for CI4 on the int8 path also windows of at most
- *        (2^31 - 1) / (128 max_abs^2) samples (its operands are the samples times 8).
+ *        (2^31 - 1) / (256 max_abs^2) samples (its operands are the samples times 8, or 16
+ *        on the row side of a rectangle).
  *        Same alignment fallback.
  * All shapes give bit-identical visibilities.  XCORR_ERR_INVALID_ARG for a shape the job
  * does not allow (the handle keeps its previous shape).  Resets the kernel variant to 0 and

@@ -82,11 +82,12 @@ bool super_kernel_ok(int nin, int nchan, int64_t window, int in_fmt, int acc, in
     // the copy offsets of a block (32 rows) stay below 2^32 bytes
     if (32 * (int64_t)nchan * nin * (int64_t)in_sample_bytes(in_fmt) >= ((int64_t)1 << 32)) return false;
     // fp8 operands and int8 operands from 8-bit samples are the samples themselves (the
-    // usual windows); int8 operands from 4-bit samples are 8 x the samples, so every window
-    // must stay within the int32 limit of the scaled sums
+    // usual windows); int8 operands from 4-bit samples are 8 x the samples (16 x on the
+    // rectangles' row side), so every window must stay within the int32 limit of the
+    // scaled sums, at most 2 (16 m) (8 m) per sample
     if (acc == ACC_F8 || in_fmt == IN_CI8) return true;
     const int64_t m = max_abs;
-    return m >= 1 && window <= (int64_t)2147483647 / (128 * m * m);
+    return m >= 1 && window <= (int64_t)2147483647 / (256 * m * m);
 }
 
 int64_t computed_pairs_per_sample(int nin, int tile, int acc)
@@ -228,7 +229,7 @@ int make_plan(int nstation, int npol, int nchan, int ntime, int in_fmt, int acc,
                    : tile_override == SUPER_TILE
                        ? "tile 512 (super-tiles) needs CI4 input on the int8 or fp8 path or CI8 input on the int8 "
                          "path, nin a multiple of 16 in 272..2048, and for CI4 on the int8 path windows of at most "
-                         "(2^31-1) / (128 max_abs^2) samples"
+                         "(2^31-1) / (256 max_abs^2) samples"
                        : "unsupported tile size";
             return XCORR_ERR_INVALID_ARG;
         }

@@ -52,7 +52,7 @@ constexpr int SUPER_TILE = 512;
 
 // Whether the super-tiled kernel accepts a job: CI4 samples on the int8 or fp8 path or CI8
 // samples on the int8 path, nin a multiple of 16 in 272..2048; for CI4 on the int8 path
-// also windows within the exact limit of its scaled operands (floor((2^31-1)/(128 m^2))
+// also windows within the exact limit of its scaled operands (floor((2^31-1)/(256 m^2))
 // samples for samples bounded by m).
 bool super_kernel_ok(int nin, int nchan, int64_t window, int in_fmt, int acc, int max_abs);
 

@@ -13,8 +13,11 @@
 // XOR-swizzled by row; 8-bit samples are only moved into that layout):
 //   * int8: both components scaled by 8, exactly: 8 re = ((b & 0xF0) >> 1) | (b & 0x80) per
 //     byte, and the same after moving the low nibble up; the products carry a factor 64,
-//     divided out exactly before the stores (the planner keeps such jobs to one window of
-//     floor((2^31 - 1) / (128 m^2)) samples);
+//     divided out exactly before the stores.  In the rectangles the row segment, whose
+//     operand is never negated, is scaled by 16 instead (16 re = b & 0xF0, a mask alone;
+//     -8 becomes -128, which only the rotated column operand could not hold), so their
+//     products carry 128; the planner keeps such jobs to windows of
+//     floor((2^31 - 1) / (256 m^2)) samples;
 //   * fp8: e4m3 pairs (all of -8..7 are exact), with the usual fp32 windows.
 // The K-steps (software pipelined, Sec. 4.4's staging re-planned for gfx950), rotations and
 // stores are those of the whole-channel kernel.  Variant bit 1 (rectangles): the widening
@@ -172,6 +175,15 @@ __device__ __forceinline__ void ci4x4_to_e4m3x8(uint32_t w, uint32_t &lo, uint32
     hi = __builtin_amdgcn_perm(im, re, 0x07030602u);
 }
 
+// 16 x the samples (rectangles' row segment): the nibbles in the high half of each byte.
+__device__ __forceinline__ void ci4x4_to_i8x16(uint32_t w, uint32_t &lo, uint32_t &hi)
+{
+    const uint32_t re = w & 0xF0F0F0F0u;
+    const uint32_t im = (w << 4) & 0xF0F0F0F0u;
+    lo = __builtin_amdgcn_perm(im, re, 0x05010400u);
+    hi = __builtin_amdgcn_perm(im, re, 0x07030602u);
+}
+
 __device__ __forceinline__ void ci4x4_to_i8x8(uint32_t w, uint32_t &lo, uint32_t &hi)
 {
     const uint32_t t = w & 0xF0F0F0F0u;
@@ -209,21 +221,27 @@ __device__ __forceinline__ void ci4x4_to_e4m3x8_rot(uint32_t w, uint32_t &lo, ui
     hi = __builtin_amdgcn_perm(re, nim, 0x07030602u);
 }
 
-// int8 from 4-bit samples: the operands are 8 x the samples, the sums 64 x the
-// visibilities (exact shift)
-template <int ACC, int IN, typename S>
+// int8 from 4-bit samples: the sums are 64 x the visibilities (triangles: both operands 8 x
+// the samples) or 128 x (rectangles: 16 x and 8 x), exact shifts
+template <int ACC, int IN, int TRI, typename S>
 __device__ __forceinline__ void descale_store(const XJob &p, int f, int lane, AccSet<ACC> &acc, int row_base,
                                               int col_base)
 {
     if constexpr (ACC == ACC_I8 && IN == IN_CI4) {
+        constexpr int SH = TRI ? 6 : 7;
 #pragma unroll
         for (int x = 0; x < S::NB; ++x) {
-            acc.re[x] = acc.re[x] >> 6;
-            acc.im[x] = acc.im[x] >> 6;
+            acc.re[x] = acc.re[x] >> SH;
+            acc.im[x] = acc.im[x] >> SH;
         }
     }
     store_all<ACC, S>(p, f, lane, acc, row_base, col_base);
 }
+
+// Widening kind of unit instruction M (see run_wave_super): row-segment units of a
+// rectangle widen to 16 x the samples, the rest to 8 x, the fourth unit is rotated.
+template <int TRI, int M>
+constexpr int unit_kind_v = M < 2 ? (TRI ? 0 : 2) : (M == 2 ? 0 : 1);
 
 template <int ACC, int IN, int TRI, int W, int V>
 __device__ __forceinline__ void run_wave_super(const XJob &p, int lane)
@@ -239,7 +257,6 @@ __device__ __forceinline__ void run_wave_super(const XJob &p, int lane)
                                         typename std::conditional<PRE, RectRotSpec<W>, RectSpec<W>>::type>::type;
     constexpr int NUP = TRI ? 2 : 3;    // plain widening instructions per wave per block
     constexpr int NU = NUP + (PRE ? 1 : 0);  // and one of rotated column chunks with PRE
-    constexpr int NCH = TRI ? 32 : 48;  // 16-byte chunks of a plain widened row
     const uint64_t row_stride = (uint64_t)p.nchan * p.nin * Gs::BPS;
     const uint32_t lds0 = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) uint8_t *)chan_lds;
     const uint32_t conv0 = lds0 + RING * Gs::RAW;
@@ -267,32 +284,35 @@ __device__ __forceinline__ void run_wave_super(const XJob &p, int lane)
                   voff_b);
     };
 
-    // widening units: instruction m < NUP of wave W covers unit U = 512 m + 64 W + lane, row
-    // U / NCH, chunk U % NCH (chunks 0..31 from segment A, 32..47 from segment B); with PRE,
-    // instruction NUP covers rotated unit U = 64 W + lane, row U / 16, chunk 48 + U % 16
-    // from chunk U % 16 of segment B
-    static_assert(NUP * 512 == SP_TB * NCH && (!PRE || 512 == SP_TB * 16), "units cover the block");
+    // widening units, one 16-byte chunk of a widened row each: instructions m = 0, 1 of
+    // wave W cover row-segment unit U = 512 m + 64 W + lane (row U / 32, chunk U % 32); in a
+    // rectangle instruction 2 covers column-segment unit U = 64 W + lane (row U / 16, chunk
+    // 32 + U % 16) and, with PRE, instruction 3 its rotated copy (chunk 48 + U % 16)
+    static_assert(SP_TB * 32 == 1024 && SP_TB * 16 == 512, "units cover the block");
     uint32_t usrc[NU], udst[NU];
 #pragma unroll
-    for (int m = 0; m < NUP; ++m) {
+    for (int m = 0; m < 2; ++m) {
         const int U = 512 * m + 64 * W + lane;
-        const int row = U / NCH, c = U - NCH * (U / NCH);
-        usrc[m] = (uint32_t)(c < 32 ? row * Gs::AROW + Gs::UB * c
-                                    : SP_TB * Gs::AROW + row * Gs::BROW + Gs::UB * (c - 32));
+        const int row = U >> 5, c = U & 31;
+        usrc[m] = (uint32_t)(row * Gs::AROW + Gs::UB * c);
         udst[m] = (uint32_t)(row * CROW_W + 16 * (c ^ (4 * (row & 3))));
     }
-    if constexpr (PRE) {
+#pragma unroll
+    for (int m = 2; m < NU; ++m) {
         const int U = 64 * W + lane;
-        const int row = U >> 4, r = U & 15, c = 48 + r;
-        usrc[NUP] = (uint32_t)(SP_TB * Gs::AROW + row * Gs::BROW + Gs::UB * r);
-        udst[NUP] = (uint32_t)(row * CROW_W + 16 * (c ^ (4 * (row & 3))));
+        const int row = U >> 4, r = U & 15, c = (m == 2 ? 32 : 48) + r;
+        usrc[m] = (uint32_t)(SP_TB * Gs::AROW + row * Gs::BROW + Gs::UB * r);
+        udst[m] = (uint32_t)(row * CROW_W + 16 * (c ^ (4 * (row & 3))));
     }
     typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
     typedef __attribute__((address_space(3))) u32x2 lds_u2;
     // raw unit: 8 bytes of 4-bit samples, or 16 bytes of 8-bit samples (already int8 pairs)
     using raw_t = typename std::conditional<IN == IN_CI8, u32x4, u32x2>::type;
-    auto widen = [&](raw_t v, uint32_t dst, auto RotTag) __attribute__((always_inline)) {
-        constexpr bool ROTU = decltype(RotTag)::value;
+    // kind 0: 8 x the samples (int8) or e4m3; 1: the same rotated to (-im, re); 2: the
+    // rectangles' row segment (16 x the samples on the int8 path)
+    auto widen = [&](raw_t v, uint32_t dst, auto KindTag) __attribute__((always_inline)) {
+        constexpr int KIND = decltype(KindTag)::value;
+        constexpr bool ROTU = KIND == 1;
         if constexpr (IN == IN_CI8) {
             static_assert(ACC == ACC_I8, "8-bit samples: int8 path only");
             if constexpr (ROTU)
@@ -302,7 +322,10 @@ __device__ __forceinline__ void run_wave_super(const XJob &p, int lane)
                 *(lds_u4 *)(uintptr_t)dst = v;
         } else {
             uint32_t o0, o1, o2, o3;
-            if constexpr (ACC == ACC_I8 && ROTU) {
+            if constexpr (ACC == ACC_I8 && KIND == 2) {
+                ci4x4_to_i8x16(v[0], o0, o1);
+                ci4x4_to_i8x16(v[1], o2, o3);
+            } else if constexpr (ACC == ACC_I8 && ROTU) {
                 ci4x4_to_i8x8_rot(v[0], o0, o1);
                 ci4x4_to_i8x8_rot(v[1], o2, o3);
             } else if constexpr (ACC == ACC_I8) {
@@ -326,7 +349,7 @@ __device__ __forceinline__ void run_wave_super(const XJob &p, int lane)
     auto widen_block = [&](uint32_t src, uint32_t dst) __attribute__((always_inline)) {
         static_for<NU>([&](auto M) __attribute__((always_inline)) {
             constexpr int m = decltype(M)::value;
-            widen(raw_read(src + usrc[m]), dst + udst[m], std::integral_constant<bool, (m >= NUP)>{});
+            widen(raw_read(src + usrc[m]), dst + udst[m], std::integral_constant<int, unit_kind_v<TRI, m>>{});
         });
     };
 
@@ -390,7 +413,7 @@ __device__ __forceinline__ void run_wave_super(const XJob &p, int lane)
             static_for<NU>([&](auto U) __attribute__((always_inline)) {
                 constexpr int u = decltype(U)::value;
                 if constexpr (u * NKS / NU == decltype(K)::value)
-                    widen(rr[u], cdst + udst[u], std::integral_constant<bool, (u >= NUP)>{});
+                    widen(rr[u], cdst + udst[u], std::integral_constant<int, unit_kind_v<TRI, u>>{});
             });
         };
         block_raw<ACC, S, NKS, CROW_W>(lv, acc, copy, mid, pre);
@@ -401,7 +424,7 @@ __device__ __forceinline__ void run_wave_super(const XJob &p, int lane)
         if (++cc.blk == cc.nblk) {
             wait_vm<0>();
             ready = RING - 2;
-            descale_store<ACC, IN, S>(p, cc.f, lane, acc, cc.seg_a, cc.seg_b);
+            descale_store<ACC, IN, TRI, S>(p, cc.f, lane, acc, cc.seg_a, cc.seg_b);
 #pragma unroll
             for (int x = 0; x < MAXB; ++x) {
                 acc.re[x] = (acc_t){};

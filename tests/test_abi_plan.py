@@ -232,8 +232,9 @@ def test_super_tile_plan():
     # computed pairs: 4 x 36 blocks + 12 x 32 blocks of 32 x 32
     assert p["computed_cmacs"] == (4 * 36 + 12 * 32) * 1024 * 256 * 4096
     assert p["useful_cmacs"] == 1024 * 1025 // 2 * 256 * 4096
-    # the operands are 8 x the samples: one window of floor((2^31-1) / (128 m^2)) samples
-    lim = (2 ** 31 - 1) // (128 * 8 * 8)
+    # the operands are 8 x the samples (16 x on a rectangle's row side): one window of
+    # floor((2^31-1) / (256 m^2)) samples
+    lim = (2 ** 31 - 1) // (256 * 8 * 8)
     X.xcorr_plan(256, 2, 2, lim, X.IN_CI4, X.ACC_I8_MMA_I32, 0, 512)
     with pytest.raises(X.XcorrError):
         X.xcorr_plan(256, 2, 2, lim + 1, X.IN_CI4, X.ACC_I8_MMA_I32, 0, 512)
@@ -314,10 +315,10 @@ def test_requested_windows():
 
 
 def test_super_tiles_with_requested_windows():
-    """4-bit samples on the int8 super-tiles carry 8x operands: an integration longer than
-    their scaled limit (262143 samples) runs on super-tiles once windows within that limit
-    are requested."""
-    lim = (2**31 - 1) // (128 * 64)
+    """4-bit samples on the int8 super-tiles carry 8x and 16x operands: an integration
+    longer than their scaled limit (131071 samples) runs on super-tiles once windows within
+    that limit are requested."""
+    lim = (2**31 - 1) // (256 * 64)
     with pytest.raises(X.XcorrError):
         X.xcorr_plan(256, 2, 2, lim + 1, X.IN_CI4, X.ACC_I8_MMA_I32, 0, 512)
     p = X.xcorr_plan(256, 2, 2, lim + 1, X.IN_CI4, X.ACC_I8_MMA_I32, 0, 512, lim)

@@ -195,15 +195,15 @@ def test_int8_ci4_window_bound_tiles(oracle_mod):
 
 
 def test_int8_ci4_window_bound_super(oracle_mod):
-    """4-bit samples on the int8 super-tiles carry operands 8 x the samples: -8 - 8i gives
-    2 * 64^2 = 8192 per sample, so windows hold at most 262143 samples (2^31 - 8192 at the
-    bound).  T = 262143 in one window on super-tiles; T = 262144 runs two requested windows
-    of 262143 samples (int64 totals)."""
+    """4-bit samples on the int8 super-tiles carry operands 8 x the samples, 16 x on the row
+    side of a rectangle: -8 - 8i gives 2 * 128 * 64 = 16384 per sample there, so windows hold
+    at most 131071 samples (2^31 - 16384 at the bound).  T = 131071 in one window on
+    super-tiles; T = 131072 runs two requested windows of 131071 samples (int64 totals)."""
     from paper_1107_4264_amd import xcorr as X
 
     ns, npol, F = 136, 2, 1
-    lim = (2**31 - 1) // (128 * 8 * 8)
-    assert lim == 262143 and lim * 8192 <= 2**31 - 1 < (lim + 1) * 8192
+    lim = (2**31 - 1) // (256 * 8 * 8)
+    assert lim == 131071 and lim * 16384 <= 2**31 - 1 < (lim + 1) * 16384
     for T, window, want_type in ((lim, None, X.OUT_CI32), (lim + 1, lim, X.OUT_CI64)):
         x = constant_worst_ci4(T, F, ns * npol)
         say("int8 ci4 super window bound", T, window)
