@@ -164,9 +164,11 @@ int xcorr_set_staging(xcorr_handle_t *h, int staging);
 int xcorr_get_staging(const xcorr_handle_t *h);
 
 /* Compile-time variant of the kernel (the tuning parameters of Sec. 4.3 / 4.4 fixed per
- * kernel build): whole-channel kernel (tile 256) 0..3 — bit 0 keeps one time block fewer in
- * the LDS copy ring (int8: 3 instead of 4 blocks of 64 samples; fp16: 4 instead of 5 of
- * 32), bit 1 swaps which of the two waves sharing a SIMD takes the five-block work list;
+ * kernel build): whole-channel kernel (tile 256) 0..3, fp16 0..7 — bit 0 keeps one time
+ * block fewer in the LDS copy ring (int8: 3 instead of 4 blocks of 64 samples; fp16: 4
+ * instead of 5 of 32), bit 1 swaps which of the two waves sharing a SIMD takes the
+ * five-block work list, bit 2 (fp16) converts each block to fp16 on all eight waves
+ * instead of the four five-block waves;
  * super-tiles (tile 512) 0..3 — bit 0 uses a three-block instead of a four-block ring, bit 1
  * stages the rectangles' column operands also in rotated (-im, re) form, so that no wave
  * rotates a fragment; the other kernels have variant 0 only.  XCORR_ERR_INVALID_ARG outside that range.  Same

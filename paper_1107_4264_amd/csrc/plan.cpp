@@ -119,7 +119,7 @@ int64_t computed_pairs_per_sample(int nin, int tile, int acc)
 int kernel_variants(int tile, int acc)
 {
     if (acc == ACC_F32_CMAC) return 1;
-    if (tile == CHAN_TILE) return 4;
+    if (tile == CHAN_TILE) return acc == ACC_F16 ? 8 : 4;
     if (tile == SUPER_TILE) return 4;
     return 1;
 }
@@ -237,7 +237,7 @@ int make_plan(int nstation, int npol, int nchan, int ntime, int in_fmt, int acc,
     }
     p.tile = tile;
     if (variant < 0 || variant >= kernel_variants(tile, acc)) {
-        *err = "kernel variant out of range for the kernel shape (whole channel 0..3, super-tiles 0..3, others 0)";
+        *err = "kernel variant out of range for the kernel shape (whole channel 0..3, fp16 0..7, super-tiles 0..3, others 0)";
         return XCORR_ERR_INVALID_ARG;
     }
     p.variant = variant;

@@ -15,7 +15,7 @@ struct Plan {
     int window = 0, nwindows = 0, out_dtype = 0;
     int window_req = 0;  // window the caller asked for (0: the longest exact one)
     int staging = 0;     // 0: operands staged in LDS; 1: loaded per wave through the caches
-    int variant = 0;     // compile-time variant of the whole-channel (0..3) / super-tiled (0..3) kernel
+    int variant = 0;     // compile-time variant of the whole-channel (0..3, fp16 0..7) / super-tiled (0..3) kernel
     int64_t nitems = 0, useful_cmacs = 0, computed_cmacs = 0;
     size_t in_bytes = 0, out_bytes = 0;
 };

@@ -29,7 +29,7 @@ bool valid_val(const TuneVal &v)
 {
     const bool tile_ok = v.tile == 64 || v.tile == 128 || v.tile == 256 || v.tile == 512;
     const bool staging_ok = v.staging == 0 || (v.staging == 1 && (v.tile == 64 || v.tile == 128));
-    const int nvar = v.tile == 256 || v.tile == 512 ? 4 : 1;
+    const int nvar = v.tile == 256 ? 8 : (v.tile == 512 ? 4 : 1);
     return tile_ok && staging_ok && v.variant >= 0 && v.variant < nvar && v.us >= 0.0;
 }
 

@@ -128,14 +128,16 @@ __device__ __forceinline__ void run_wave(const XJob &p, int lane)
     } else {
         // Staged operands: the block after the one being multiplied is converted into the
         // other buffer (unit of input i and samples 4q..4q+3 at 4096 q + 16 i), read from the
-        // raw ring with transposing reads.  Only the waves with five blocks (0..3) convert:
-        // the four-block waves share their SIMDs with them and are the ones the barriers
-        // wait for.  Instruction u of converting wave W covers the 16-input group
-        // ig = 4 (u % 4) + lane / 16 at sample group q = 2 W + u / 4; units u and u + 4 differ
-        // by four sample rows.
-        constexpr int CW = 4;                          // converting waves
+        // raw ring with transposing reads.  By default only the waves with five blocks (0..3)
+        // convert: the four-block waves share their SIMDs with them and are the ones the
+        // barriers wait for; variant bit 2 spreads the conversion over all eight waves.
+        // Instruction u of converting wave W covers the 16-input group ig = 4 (u % 4) +
+        // lane / 16 at sample group q = (UPW / 4) W + u / 4; units u and u + 4 differ by four
+        // sample rows.
+        constexpr int CW = (V & 4) ? 8 : 4;            // converting waves
         constexpr int UPW = 16 * G::QUADS / 4 / CW;    // conversion instructions per converting wave
-        static_assert(UPW == 2 * NKS, "two conversion units per K-step");
+        constexpr int UPK = UPW / NKS;                 // of them per K-step
+        static_assert(UPK * NKS == UPW && UPK >= 1 && UPK <= 2, "whole conversion units per K-step");
         const uint32_t fb0 = lds0 + RING * G::BLK;
         uint32_t cin[4], cout[4];
 #pragma unroll
@@ -194,18 +196,18 @@ __device__ __forceinline__ void run_wave(const XJob &p, int lane)
                     constexpr int k = decltype(K)::value;
                     Frag<4>(&cur)[S::NF] = (k & 1) ? fbk : fa;
                     Frag<4>(&nxt)[S::NF] = (k & 1) ? fa : fbk;
-                    s16x4 cv0, cv1;
+                    s16x4 cv[UPK];
                     if constexpr (W < CW) {
-                        cv0 = convert_read(2 * k, csrc);
-                        cv1 = convert_read(2 * k + 1, csrc);
+#pragma unroll
+                        for (int j = 0; j < UPK; ++j) cv[j] = convert_read(UPK * k + j, csrc);
                     }
                     if constexpr (k + 1 < NKS) read_staged<S, k + 1>(lvf, nxt);
                     __builtin_amdgcn_sched_barrier(0);
                     mma_step<ACC, S>(cur, acc, [&]() __attribute__((always_inline)) { copy_at(K, rs, dst); },
                                      [&]() __attribute__((always_inline)) {
                                          if constexpr (W < CW) {
-                                             convert_write(2 * k, cv0, cdst);
-                                             convert_write(2 * k + 1, cv1, cdst);
+#pragma unroll
+                                             for (int j = 0; j < UPK; ++j) convert_write(UPK * k + j, cv[j], cdst);
                                          }
                                      });
                 });
@@ -225,7 +227,7 @@ __device__ __forceinline__ void run_wave(const XJob &p, int lane)
 }
 
 // Variant V: bit 0 one ring slot fewer (Geom), bit 1 the other assignment of the work lists
-// to the older and younger wave of each SIMD.
+// to the older and younger wave of each SIMD, bit 2 (fp16) the conversion on all eight waves.
 template <int ACC, int V>
 __global__ __launch_bounds__(CT, 1) void xeng_chan_kernel(XJob p)
 {
@@ -265,8 +267,18 @@ int launch_chan_acc(const XJob &job, hipStream_t stream)
     case 1: return launch_chan_var<ACC, 1>(job, stream);
     case 2: return launch_chan_var<ACC, 2>(job, stream);
     case 3: return launch_chan_var<ACC, 3>(job, stream);
-    default: return (int)hipErrorInvalidValue;
+    default: break;
     }
+    if constexpr (ACC == ACC_F16) {
+        switch (job.variant) {
+        case 4: return launch_chan_var<ACC, 4>(job, stream);
+        case 5: return launch_chan_var<ACC, 5>(job, stream);
+        case 6: return launch_chan_var<ACC, 6>(job, stream);
+        case 7: return launch_chan_var<ACC, 7>(job, stream);
+        default: break;
+        }
+    }
+    return (int)hipErrorInvalidValue;
 }
 
 }  // namespace

@@ -126,13 +126,32 @@ def test_super_variant(oracle_mod, fmt_acc, shape, variant):
     _check(got, want, f"super-variant/{fmt}/{acc}/{shape}")
 
 
+@pytest.mark.parametrize("variant", [4, 5, 6, 7])
+@pytest.mark.parametrize("shape", [(128, 2, 5, 1000), (100, 2, 3, 257), (256, 1, 2, 130)],
+                         ids=lambda s: "x".join(map(str, s)))
+def test_chan_f16_conversion_on_all_waves(oracle_mod, variant, shape):
+    """fp16 whole-channel variants 4..7: the conversion of each block spread over all eight
+    waves (with the ring-depth and wave-order bits)."""
+    ns, npol, F, T = shape
+    x = synth.voltages_np(5250 + variant, T, F, ns * npol, ("gauss", 40.0, 127))
+    say("chan f16 variant", variant, shape)
+    got, sh = _run(x, ns, npol, "ci8", "f16", tile=256, variant=variant)
+    assert sh == (256, 0, variant)
+    _check(got, oracle_mod.xcorr(x, ns, npol), f"chan-f16-variant/{variant}/{shape}")
+
+
 def test_variant_range_checked():
     from paper_1107_4264_amd import xcorr as X
 
     device()
     c = X.Correlator(128, 2, 2, 10, "ci8", "f16")
     with pytest.raises(X.XcorrError):
-        X.xcorr_set_variant(c.h, 4)
+        X.xcorr_set_variant(c.h, 8)
+    i = X.Correlator(128, 2, 2, 10, "ci8", "i8")
+    assert i.tile == 256
+    with pytest.raises(X.XcorrError):
+        X.xcorr_set_variant(i.h, 4)
+    i.close()
     X.xcorr_set_tile(c.h, 128)
     with pytest.raises(X.XcorrError):
         X.xcorr_set_variant(c.h, 1)
