@@ -137,8 +137,14 @@ def main():
         tuned = None
         if p in paths and acc != "f32" and not args.tile and not args.no_autotune:
             # the paths of the workload run the shape the autotuner picks for them (every
-            # tile x staging x variant the job allows, timed on the device)
-            c.autotune(x, out, reps=5)
+            # tile x staging x variant the job allows, timed on the device), timed once the
+            # clocks have ramped up under the default shape
+            t_ramp = time.perf_counter()
+            while time.perf_counter() - t_ramp < args.ramp_seconds:
+                for _ in range(10):
+                    c.run(x, out)
+                torch.cuda.synchronize()
+            c.autotune(x, out, reps=20)
             tuned = [{k: (round(v, 2) if isinstance(v, float) else v) for k, v in r.items()}
                      for r in X.xcorr_autotune_results(c.h)]
         plan = X.xcorr_plan(ns, npol, F, T, in_enum, X.ACC_NAMES[acc], max_abs, c.tile)
