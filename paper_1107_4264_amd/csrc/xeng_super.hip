@@ -131,15 +131,24 @@ struct SCursor {
     }
 };
 
-// Descriptor of one input segment of the block the cursor points at (bytes `len` of each
-// row from input `first`, bps bytes per sample); len 0 reads zeros.
+// Byte address of input 0 in the first row of the block the cursor points at.
 template <typename C>
-__device__ __forceinline__ i32x4s seg_rsrc(const XJob &p, const C &c, int first, int len, uint64_t row_stride,
+__device__ __forceinline__ uint64_t block_base(const XJob &p, const C &c, int bps)
+{
+    const int r0 = c.t0 + c.blk * SP_TB;
+    return (uint64_t)p.in + (((uint64_t)r0 * p.nchan + c.f) * (uint64_t)p.nin) * bps;
+}
+
+// Descriptor of one input segment of the block the cursor points at, whose input 0 is at
+// `bbase` (block_base): bytes `len` of each row from input `first`, bps bytes per sample;
+// len 0 reads zeros.
+template <typename C>
+__device__ __forceinline__ i32x4s seg_rsrc(uint64_t bbase, const C &c, int first, int len, uint64_t row_stride,
                                            int bps)
 {
     const int r0 = c.t0 + c.blk * SP_TB;
     const int nrows = len ? max(0, min(SP_TB, c.t1 - r0)) : 0;
-    const uint64_t base = (uint64_t)p.in + (((uint64_t)r0 * p.nchan + c.f) * (uint64_t)p.nin + first) * bps;
+    const uint64_t base = bbase + (uint64_t)(first * bps);
     const uint32_t nrec = nrows ? (uint32_t)((nrows - 1) * row_stride + len) : 0u;
     i32x4s r;
     r[0] = __builtin_amdgcn_readfirstlane((int)(uint32_t)base);
@@ -273,15 +282,22 @@ __device__ __forceinline__ void run_wave_super(const XJob &p, int lane)
     const uint32_t voff_b = (uint32_t)((ib * (1024 / Gs::BROW) + lane / LB) * row_stride + 16 * (lane % LB));
     // The last super-row may be partial (nin not a multiple of 256): its chunks past the
     // last input read zeros (the rows below would otherwise hold the next channel).
-    auto issue = [&](const SCursor<TRI> &c, int slot, int m) __attribute__((always_inline)) {
+    // the address of a block's input 0 advances by SP_TB rows per block within an item
+    const uint64_t blk_bytes = (uint64_t)SP_TB * row_stride;
+    auto issue = [&](const SCursor<TRI> &c, uint64_t bbase, int slot, int m) __attribute__((always_inline)) {
         const uint32_t sb = lds0 + slot * Gs::RAW;
         if (m < NAW) {
             const int va = min(Gs::AROW, (p.nin - c.seg_a) * Gs::BPS);  // valid bytes of a row
             const uint32_t vo = 16 * (lane % LA) < va ? voff_a[m] : COOB;
-            dma16(seg_rsrc(p, c, c.seg_a, va, row_stride, Gs::BPS), sb + (8 * m + W) * 1024, vo);
+            dma16(seg_rsrc(bbase, c, c.seg_a, va, row_stride, Gs::BPS), sb + (8 * m + W) * 1024, vo);
         } else
-            dma16(seg_rsrc(p, c, c.seg_b, TRI ? 0 : Gs::BROW, row_stride, Gs::BPS), sb + SP_TB * Gs::AROW + ib * 1024,
-                  voff_b);
+            dma16(seg_rsrc(bbase, c, c.seg_b, TRI ? 0 : Gs::BROW, row_stride, Gs::BPS),
+                  sb + SP_TB * Gs::AROW + ib * 1024, voff_b);
+    };
+    // dc.next with its block address kept up to date (recomputed only at a new item)
+    auto advance = [&](SCursor<TRI> &c, uint64_t &bbase) __attribute__((always_inline)) {
+        c.next(p);
+        bbase = c.blk == 0 ? block_base(p, c, Gs::BPS) : bbase + blk_bytes;
     };
 
     // widening units, one 16-byte chunk of a widened row each: instructions m = 0, 1 of
@@ -368,11 +384,12 @@ __device__ __forceinline__ void run_wave_super(const XJob &p, int lane)
     dc.init(p);
     cc.init(p);
     nc.init(p);
+    uint64_t dbase = block_base(p, dc, Gs::BPS);
 #pragma unroll
     for (int d = 0; d < RING - 1; ++d) {
 #pragma unroll
-        for (int m = 0; m < DPW; ++m) issue(dc, d, m);
-        dc.next(p);
+        for (int m = 0; m < DPW; ++m) issue(dc, dbase, d, m);
+        advance(dc, dbase);
     }
     nc.next(p);  // the block after cc's
 
@@ -387,8 +404,9 @@ __device__ __forceinline__ void run_wave_super(const XJob &p, int lane)
         else --ready;
         __syncthreads();
         const SCursor<TRI> ic = dc;
+        const uint64_t ibase = dbase;
         const int dslot = slot == 0 ? RING - 1 : slot - 1;
-        dc.next(p);
+        advance(dc, dbase);
         const uint32_t csrc = lds0 + (slot == RING - 1 ? 0 : slot + 1) * Gs::RAW;
         const uint32_t cdst = conv0 + (fb ^ 1) * CONV;
         uint32_t lv[4];
@@ -400,7 +418,7 @@ __device__ __forceinline__ void run_wave_super(const XJob &p, int lane)
         raw_t rr[NU];
         auto copy = [&](auto K) __attribute__((always_inline)) {
             static_for<DPW>([&](auto M) __attribute__((always_inline)) {
-                if constexpr (decltype(M)::value * NKS / DPW == decltype(K)::value) issue(ic, dslot, decltype(M)::value);
+                if constexpr (decltype(M)::value * NKS / DPW == decltype(K)::value) issue(ic, ibase, dslot, decltype(M)::value);
             });
         };
         auto pre = [&](auto K) __attribute__((always_inline)) {
