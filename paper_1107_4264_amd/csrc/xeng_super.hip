@@ -148,7 +148,7 @@ __device__ __forceinline__ i32x4s seg_rsrc(uint64_t bbase, const C &c, int first
 {
     const int r0 = c.t0 + c.blk * SP_TB;
     const int nrows = len ? max(0, min(SP_TB, c.t1 - r0)) : 0;
-    const uint64_t base = bbase + (uint64_t)(first * bps);
+    const uint64_t base = bbase + (uint64_t)(uint32_t)(first * bps);
     const uint32_t nrec = nrows ? (uint32_t)((nrows - 1) * row_stride + len) : 0u;
     i32x4s r;
     r[0] = __builtin_amdgcn_readfirstlane((int)(uint32_t)base);
