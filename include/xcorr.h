@@ -44,7 +44,9 @@
  *                             accumulation; e3m2 holds every integer of [-8, 8] exactly
  *                             (Sec. 2.3's few-bit digitised data), so it accepts CI4, or
  *                             CI8 after xcorr_set_max_abs(h, m) with m <= 8; otherwise the
- *                             run is refused with XCORR_ERR_UNSUPPORTED.  Tiled kernel.
+ *                             run is refused with XCORR_ERR_UNSUPPORTED.  Tiled kernel, or
+ *                             for CI4 the super-tiles (tile 512, after a pre-pass that
+ *                             packs every 32-sample block of each input once).
  *
  * Exactness and the output type.  Integer samples with |component| <= max_abs grow any
  * accumulator by at most 2*max_abs^2 per sample.  The library integrates in windows of at
@@ -140,10 +142,16 @@ int xcorr_set_max_abs(xcorr_handle_t *h, int max_abs);
  *        128-tiles instead;
  *   512  super-tiles: the triangle of each channel cut into 256-input triangles and
  *        256 x 128 rectangles, each held by one persistent workgroup (two launches); needs
- *        CI4 input on the int8 or fp8 path, or CI8 input on the int8 path, and nin a
+ *        CI4 input on the int8, fp8 or fp6 path, or CI8 input on the int8 path, and nin a
  *        multiple of 16 in 272..2048; for CI4 on the int8 path also windows of at most
  *        (2^31 - 1) / (256 max_abs^2) samples (its operands are the samples times 8, or 16
- *        on the row side of a rectangle).
+ *        on the row side of a rectangle); on the fp6 path windows of a multiple of 32
+ *        samples (or one window), and a workspace the handle allocates on its first run
+ *        or autotune with this shape (48 bytes per input, padded to a multiple of 256
+ *        inputs, per 32-sample block per channel: 1.5 x the input bytes plus the padding;
+ *        held until xcorr_destroy; the first run must not be inside a graph capture, else
+ *        XCORR_ERR_UNSUPPORTED; XCORR_ERR_OOM if it cannot be allocated).  The batch and
+ *        stream entry points have no such workspace and run fp6 jobs on 128-tiles.
  *        Same alignment fallback.
  * All shapes give bit-identical visibilities.  XCORR_ERR_INVALID_ARG for a shape the job
  * does not allow (the handle keeps its previous shape).  Resets the kernel variant to 0 and
@@ -171,7 +179,7 @@ int xcorr_get_staging(const xcorr_handle_t *h);
  * instead of the four five-block waves;
  * super-tiles (tile 512) 0..3 — bit 0 uses a three-block instead of a four-block ring, bit 1
  * stages the rectangles' column operands also in rotated (-im, re) form, so that no wave
- * rotates a fragment; the other kernels have variant 0 only.  XCORR_ERR_INVALID_ARG outside that range.  Same
+ * rotates a fragment (fp6 super-tiles: 0 only); the other kernels have variant 0 only.  XCORR_ERR_INVALID_ARG outside that range.  Same
  * visibilities for every variant. */
 int xcorr_set_variant(xcorr_handle_t *h, int variant);
 int xcorr_get_variant(const xcorr_handle_t *h);
@@ -304,7 +312,7 @@ void xcorr_batch_destroy(xcorr_batch_t *b);
  * safe.  XCORR_ERR_INVALID_ARG for njobs outside 1..XCORR_NOALLOC_MAX_JOBS, null arrays or
  * pointers, or a bad max_abs; otherwise the errors of create / set_max_abs / run. */
 #define XCORR_NOALLOC_MAX_JOBS 256
-#define XCORR_NOALLOC_SCRATCH_BYTES 41472
+#define XCORR_NOALLOC_SCRATCH_BYTES 43520
 int xcorr_batch_run_noalloc(int njobs, const xcorr_job *jobs, xcorr_in_dtype in_dtype, xcorr_acc_dtype acc_dtype,
                             int max_abs, const void *const *in, void *const *out, hipStream_t stream);
 

@@ -99,14 +99,16 @@ XJob job_from_plan(const Plan &pl, const void *in, void *out)
 int launch_job(const Plan &pl, XJob j, hipStream_t stream)
 {
     if (pl.tile == CHAN_TILE || pl.tile == SUPER_TILE) {
-        if ((uintptr_t)j.in % 16 == 0) {
+        // (fp6 super-tiles need the caller's unit workspace)
+        if ((uintptr_t)j.in % 16 == 0 && (pl.tile != SUPER_TILE || pl.acc != ACC_F6 || j.work)) {
             const int cus = device_cus();
             if (cus <= 0) return (int)hipErrorNoDevice;
             if (pl.tile == SUPER_TILE) return launch_super(j, pl.acc, pl.in_fmt, cus, stream);
             j.grid = std::min<int64_t>(pl.nitems, cus);
             return launch_chan(j, pl.acc, stream);
         }
-        // the row copies need 16-byte aligned rows: run 128-tiles instead
+        // the row copies need 16-byte aligned rows (and fp6 super-tiles their workspace): run
+        // 128-tiles instead
         Plan tp;
         std::string err;
         if (make_plan(pl.nstation, pl.npol, pl.nchan, pl.ntime, pl.in_fmt, pl.acc, pl.max_abs, 128, &tp, &err,
@@ -128,8 +130,9 @@ int launch_job(const Plan &pl, XJob j, hipStream_t stream)
     return 0;
 }
 
-// Enqueue one job: zero the output when windows are summed into it, then the tile kernels.
-int enqueue_job(const Plan &pl, const void *in, void *out, hipStream_t stream)
+// Enqueue one job: zero the output when windows are summed into it, then the tile kernels
+// (`work`: the fp6 super-tiles' unit workspace, if any).
+int enqueue_job(const Plan &pl, const void *in, void *out, hipStream_t stream, void *work = nullptr)
 {
     if (exact_operand_bound(pl.acc) && pl.max_abs > exact_operand_bound(pl.acc))
         return fail(XCORR_ERR_UNSUPPORTED, "fp8 e4m3 needs max_abs <= 16, fp6 e3m2 max_abs <= 8 (call xcorr_set_max_abs)");
@@ -139,6 +142,7 @@ int enqueue_job(const Plan &pl, const void *in, void *out, hipStream_t stream)
         64.0 * (double)pl.nchan * pl.nin * (double)in_sample_bytes(pl.in_fmt) >= 4294901760.0)
         return fail(XCORR_ERR_RANGE, "nchan * nin too large: 64 samples of all channels must span < 4 GiB");
     XJob j = job_from_plan(pl, in, out);
+    j.work = work;
     int e;
     if (pl.nwindows != 1) {
         e = launch_zero(out, pl.out_bytes, stream);
@@ -202,11 +206,45 @@ struct xcorr_handle {
     std::vector<TuneVal> tuned;  // every shape the last xcorr_autotune timed
     bool validate = false;                  // xcorr_run checks the sample range first
     unsigned long long *range_dev = nullptr;  // count of the range check (8 bytes, on first use)
+    void *work = nullptr;                     // fp6 super-tiles' unit workspace (on first use)
+    size_t work_bytes = 0;
     ~xcorr_handle()
     {
         if (range_dev) (void)hipFree(range_dev);
+        if (work) (void)hipFree(work);
     }
 };
+
+namespace {
+
+// The unit workspace a plan needs (fp6 super-tiles: f6_work_bytes), allocated on first use
+// and grown when a later plan needs more; not inside a graph capture.
+int ensure_work(xcorr_handle *h, const Plan &p, hipStream_t stream)
+{
+    if (p.tile != SUPER_TILE || p.acc != ACC_F6) return XCORR_OK;
+    const size_t need = f6_work_bytes(p.nin, p.nchan, p.ntime);
+    if (need <= h->work_bytes) return XCORR_OK;
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    hipError_t e = hipStreamIsCapturing(stream, &cap);
+    if (e != hipSuccess) return hip_fail((int)e, "capture status");
+    if (cap != hipStreamCaptureStatusNone)
+        return fail(XCORR_ERR_UNSUPPORTED,
+                    "the fp6 super-tiles allocate their workspace on the first run: run once before the capture");
+    if (h->work) {
+        (void)hipFree(h->work);
+        h->work = nullptr;
+        h->work_bytes = 0;
+    }
+    e = hipMalloc(&h->work, need);
+    if (e != hipSuccess) {
+        h->work = nullptr;
+        return fail(XCORR_ERR_OOM, "fp6 unit workspace (" + std::to_string(need) + " bytes)");
+    }
+    h->work_bytes = need;
+    return XCORR_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -323,6 +361,8 @@ int xcorr_autotune(xcorr_handle_t *h, const void *in, void *out, hipStream_t str
                 }
             }
     if (cand.empty()) return fail(XCORR_ERR_UNSUPPORTED, "no kernel shape accepts this job");
+    for (const Plan &q : cand)
+        if (int rc = ensure_work(h, q, stream)) return rc;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t he;
     if ((he = hipEventCreate(&e0)) != hipSuccess || (he = hipEventCreate(&e1)) != hipSuccess) {
@@ -334,15 +374,15 @@ int xcorr_autotune(xcorr_handle_t *h, const void *in, void *out, hipStream_t str
     double best_us = 0.0;
     int rc = XCORR_OK;
     // untimed runs first, so that the first shape is not timed while the clocks ramp up
-    for (int r = 0; r < reps && rc == XCORR_OK; ++r) rc = enqueue_job(cand[0], in, out, stream);
+    for (int r = 0; r < reps && rc == XCORR_OK; ++r) rc = enqueue_job(cand[0], in, out, stream, h->work);
     for (size_t c = 0; c < cand.size() && rc == XCORR_OK; ++c) {
-        rc = enqueue_job(cand[c], in, out, stream);  // warm-up
+        rc = enqueue_job(cand[c], in, out, stream, h->work);  // warm-up
         if (rc) break;
         if ((he = hipEventRecord(e0, stream)) != hipSuccess) {
             rc = hip_fail((int)he, "autotune event");
             break;
         }
-        for (int r = 0; r < reps && rc == XCORR_OK; ++r) rc = enqueue_job(cand[c], in, out, stream);
+        for (int r = 0; r < reps && rc == XCORR_OK; ++r) rc = enqueue_job(cand[c], in, out, stream, h->work);
         if (rc) break;
         float ms = 0.0f;
         if ((he = hipEventRecord(e1, stream)) != hipSuccess || (he = hipEventSynchronize(e1)) != hipSuccess ||
@@ -361,7 +401,7 @@ int xcorr_autotune(xcorr_handle_t *h, const void *in, void *out, hipStream_t str
     (void)hipEventDestroy(e1);
     if (rc) return rc;
     // leave `out` holding the chosen shape's result (bit-identical to every other shape's)
-    if ((rc = enqueue_job(cand[best], in, out, stream)) != XCORR_OK) return rc;
+    if ((rc = enqueue_job(cand[best], in, out, stream, h->work)) != XCORR_OK) return rc;
     h->plan = cand[best];
     h->tuned = timed;
     tune_record(key_of(h->plan, current_arch()), TuneVal{h->plan.tile, h->plan.staging, h->plan.variant, best_us});
@@ -547,7 +587,8 @@ int xcorr_run(xcorr_handle_t *h, const void *in, void *out, hipStream_t stream)
                                              std::to_string(h->plan.max_abs) + ", " +
                                              std::to_string(h->plan.max_abs) + "]: nothing computed");
     }
-    return enqueue_job(h->plan, in, out, stream);
+    if (int rc = ensure_work(h, h->plan, stream)) return rc;
+    return enqueue_job(h->plan, in, out, stream, h->work);
 }
 
 void xcorr_destroy(xcorr_handle_t *h) { delete h; }

@@ -77,7 +77,8 @@ bool chan_kernel_ok(int nin, int in_fmt, int acc)
 
 bool super_kernel_ok(int nin, int nchan, int64_t window, int in_fmt, int acc, int max_abs)
 {
-    const bool fmt_ok = (in_fmt == IN_CI4 && (acc == ACC_I8 || acc == ACC_F8)) || (in_fmt == IN_CI8 && acc == ACC_I8);
+    const bool fmt_ok = (in_fmt == IN_CI4 && (acc == ACC_I8 || acc == ACC_F8 || acc == ACC_F6)) ||
+                        (in_fmt == IN_CI8 && acc == ACC_I8);
     if (!fmt_ok || nin % 16 != 0 || nin <= 256 || nin > 2048) return false;
     // the copy offsets of a block (32 rows) stay below 2^32 bytes
     if (32 * (int64_t)nchan * nin * (int64_t)in_sample_bytes(in_fmt) >= ((int64_t)1 << 32)) return false;
@@ -86,6 +87,7 @@ bool super_kernel_ok(int nin, int nchan, int64_t window, int in_fmt, int acc, in
     // rectangles' row side), so every window must stay within the int32 limit of the
     // scaled sums, at most 2 (16 m) (8 m) per sample
     if (acc == ACC_F8 || in_fmt == IN_CI8) return true;
+    if (acc == ACC_F6) return true;  // (its windows: see make_plan)
     const int64_t m = max_abs;
     return m >= 1 && window <= (int64_t)2147483647 / (256 * m * m);
 }
@@ -120,7 +122,7 @@ int kernel_variants(int tile, int acc)
 {
     if (acc == ACC_F32_CMAC) return 1;
     if (tile == CHAN_TILE) return acc == ACC_F16 ? 8 : 4;
-    if (tile == SUPER_TILE) return 4;
+    if (tile == SUPER_TILE) return acc == ACC_F6 ? 1 : 4;
     return 1;
 }
 
@@ -206,12 +208,17 @@ int make_plan(int nstation, int npol, int nchan, int ntime, int in_fmt, int acc,
     // Above 192 inputs the whole-channel kernel computes at most 36/28 of the useful blocks
     // and reads every sample once, in whole rows.
     if (chan_kernel_ok(p.nin, in_fmt, acc) && p.nin > 192 && !staging) tile = CHAN_TILE;
-    // Above 256 inputs of 4-bit samples on the int8 / fp8 paths and of 8-bit samples on the
-    // int8 path, super-tiles (whole 256-input pieces per workgroup, operands widened or moved
-    // once per block in LDS) when their padding of the last super-row costs at most 15 %
-    // more computed blocks than 128-tiles (equal at multiples of 256; the pieces run
-    // 1.15-1.3x faster per block).
-    if (!staging && super_kernel_ok(p.nin, nchan, p.window, in_fmt, acc, max_abs) &&
+    // Above 256 inputs of 4-bit samples on the int8 / fp8 / fp6 paths and of 8-bit samples on
+    // the int8 path, super-tiles (whole 256-input pieces per workgroup, operands widened or
+    // moved once per block in LDS, or on the fp6 path made once by a pre-pass) when their
+    // padding of the last super-row costs at most 15 % more computed blocks than 128-tiles
+    // (equal at multiples of 256; the pieces run 1.15-1.3x faster per block, the fp6 ones
+    // 3.5x).
+    // fp6 super-tiles: the pre-pass's units hold whole blocks of 32 samples, so every window
+    // must start on one
+    const bool super_ok = super_kernel_ok(p.nin, nchan, p.window, in_fmt, acc, max_abs) &&
+                          (acc != ACC_F6 || p.nwindows <= 1 || p.window % 32 == 0);
+    if (!staging && super_ok &&
         computed_pairs_per_sample(p.nin, SUPER_TILE, acc) * 100 <= computed_pairs_per_sample(p.nin, 128, acc) * 115)
         tile = SUPER_TILE;
     if (tile_override) {
@@ -219,7 +226,7 @@ int make_plan(int nstation, int npol, int nchan, int ntime, int in_fmt, int acc,
         if (acc == ACC_F32_CMAC) ok = tile_override == 64;
         else if (tile_override == CHAN_TILE) ok = !staging && chan_kernel_ok(p.nin, in_fmt, acc);
         else if (tile_override == SUPER_TILE)
-            ok = !staging && super_kernel_ok(p.nin, nchan, p.window, in_fmt, acc, max_abs);
+            ok = !staging && super_ok;
         else ok = tile_override == 64 || tile_override == 128;
         if (!ok) {
             *err = staging && (tile_override == CHAN_TILE || tile_override == SUPER_TILE)
@@ -227,9 +234,9 @@ int make_plan(int nstation, int npol, int nchan, int ntime, int in_fmt, int acc,
                    : tile_override == CHAN_TILE
                        ? "tile 256 (whole channel) needs CI8 input, the int8 or fp16 path and nin <= 256, a multiple of 8"
                    : tile_override == SUPER_TILE
-                       ? "tile 512 (super-tiles) needs CI4 input on the int8 or fp8 path or CI8 input on the int8 "
-                         "path, nin a multiple of 16 in 272..2048, and for CI4 on the int8 path windows of at most "
-                         "(2^31-1) / (256 max_abs^2) samples"
+                       ? "tile 512 (super-tiles) needs CI4 input on the int8, fp8 or fp6 path or CI8 input on the "
+                         "int8 path, nin a multiple of 16 in 272..2048, for CI4 on the int8 path windows of at most "
+                         "(2^31-1) / (256 max_abs^2) samples, on the fp6 path windows of whole 32-sample blocks"
                        : "unsupported tile size";
             return XCORR_ERR_INVALID_ARG;
         }
@@ -237,7 +244,8 @@ int make_plan(int nstation, int npol, int nchan, int ntime, int in_fmt, int acc,
     }
     p.tile = tile;
     if (variant < 0 || variant >= kernel_variants(tile, acc)) {
-        *err = "kernel variant out of range for the kernel shape (whole channel 0..3, fp16 0..7, super-tiles 0..3, others 0)";
+        *err = "kernel variant out of range for the kernel shape (whole channel 0..3, fp16 0..7, super-tiles 0..3, fp6 "
+                "super-tiles and others 0)";
         return XCORR_ERR_INVALID_ARG;
     }
     p.variant = variant;

@@ -44,7 +44,16 @@ struct XJob {
     int64_t nitems;       // nchan * tiles_per_chan * nwindows
     int64_t grid;         // blocks in this launch
     int64_t block0;       // item number of block 0 (launches are split below 2^24 blocks)
+    void *work;           // fp6 super-tiles: the unit workspace (f6_work_bytes), else unused
 };
+
+// Bytes of the fp6 super-tiles' unit workspace: one 48-byte unit per (channel, block of 32
+// samples, input), the inputs padded to whole super-rows of 256.
+inline size_t f6_work_bytes(int nin, int nchan, int ntime)
+{
+    const size_t npad = 256 * (size_t)((nin + 255) / 256), ntb = (size_t)((ntime + 31) / 32);
+    return (size_t)nchan * ntb * npad * 48;
+}
 
 // One entry of a batch work list: job index, channel, tile, window.
 struct XItem {
@@ -67,6 +76,8 @@ int launch_range_count(const void *in, size_t bytes, bool ci4, int max_abs, unsi
 // Whole-channel kernel (tile 256): persistent, job.grid workgroups of 512 threads walk the
 // job.nitems (channel, window) items, window-major.
 int launch_chan(const XJob &job, int acc, hipStream_t stream);
+// Super-tiles (tile 512): triangles, then rectangles, each at most `cus` workgroups; on the
+// fp6 path (CI4) first the pre-pass into job.work (f6_work_bytes; required).
 int launch_super(const XJob &job, int acc, int in_fmt, int cus, hipStream_t stream);
 
 // Batched persistent launch.  The work list is split into NQUEUE queues (one per XCD: a

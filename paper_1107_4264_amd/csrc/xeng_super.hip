@@ -507,12 +507,379 @@ int launch_super_pair(const XJob &job, int cus, hipStream_t stream)
     }
 }
 
+
+// ---------------------------------------------------------------- fp6 e3m2 super-tiles
+//
+// 4-bit samples on fp6 e3m2 operands (three exponent bits of bias 3, two mantissa bits:
+// every integer of [-8, 8] is exact) for the scaled f8f6f4 32x32x64 MFMA, at twice the
+// fp8 rate.  A pre-pass converts each (channel, block of 32 samples, input) once into a
+// 48-byte unit: the 32 real parts as e3m2 codes (six words, code k at bits 6k .. 6k + 5),
+// then the 32 imaginary parts.  Lane-half h of a fragment reads word group h of its
+// input's unit, so an MFMA of two plain fragments sums re_i re_j + im_i im_j over the
+// block (the real part of Eq. 4), and one whose row fragment is read with its halves
+// exchanged and the second half negated, (im_i, -re_i), sums im_i re_j - re_i im_j (the
+// imaginary part).  Units are stored [channel][block][input], the inputs padded with zeros
+// to whole super-rows and the last block's samples past ntime zero, so that a piece copies
+// contiguous segments (12 KiB for 256 row inputs, 6 KiB for 128 column inputs) straight
+// into LDS: the main kernel converts nothing.  Four waves, one per SIMD: in a rectangle
+// wave w computes block rows {2w, 2w + 1} x the four column blocks, in a triangle block
+// rows {w, 7 - w} (nine blocks below the diagonal); the fragments of the next block are
+// read during the MFMAs of this one.
+
+constexpr int F6_UNIT = 48;    // bytes per input per block
+constexpr int F6_CT = 512;     // threads per workgroup: eight waves, two per SIMD
+constexpr int F6_RING = 6;     // blocks in the LDS ring
+
+// e3m2 codes of four signed 4-bit values (one per byte, low nibble): byte tables of the
+// values 0..7 and -8..-1 indexed by the low three bits, chosen by the sign bit of each
+// nibble (spread to a byte mask by a third permute).
+__device__ __forceinline__ uint32_t nibbles_to_e3m2(uint32_t n)
+{
+    const uint32_t idx = n & 0x07070707u;
+    const uint32_t pos = __builtin_amdgcn_perm(0x17161514u, 0x12100C00u, idx);  // 0, 1, .., 7
+    const uint32_t neg = __builtin_amdgcn_perm(0x2C303234u, 0x35363738u, idx);  // -8, -7, .., -1
+    const uint32_t t = (n >> 3) & 0x01010101u;
+    const uint32_t m = __builtin_amdgcn_perm(0u, 0x0000FF00u, t);
+    return (neg & m) | (pos & ~m);
+}
+
+// Four 6-bit codes (one per byte) -> 24 bits, code k at bits 6k.
+__device__ __forceinline__ uint32_t pack4x6(uint32_t c)
+{
+    const uint32_t u = ((c >> 2) & 0x0FC00FC0u) | (c & 0x003F003Fu);
+    return ((u >> 4) & 0x00FFF000u) | (u & 0x00000FFFu);
+}
+
+// Eight 24-bit groups (samples 4q .. 4q + 3 in group q) -> the six words of 32 codes.
+__device__ __forceinline__ void groups_to_words(const uint32_t (&y)[8], uint32_t *w)
+{
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        w[3 * h] = y[4 * h] | (y[4 * h + 1] << 24);
+        w[3 * h + 1] = (y[4 * h + 1] >> 8) | (y[4 * h + 2] << 16);
+        w[3 * h + 2] = (y[4 * h + 2] >> 16) | (y[4 * h + 3] << 8);
+    }
+}
+
+// Pre-pass.  One thread: four consecutive inputs (one word of 4-bit samples per time row)
+// of one block of 32 samples of one channel -> their four units.  Threads run over
+// (channel, block, input group), input groups fastest: a wave reads 256 consecutive bytes
+// of each time row and writes 12 KiB of consecutive units.
+__global__ __launch_bounds__(256) void f6_pack_kernel(const uint8_t *__restrict__ in, uint8_t *__restrict__ work,
+                                                      int nin, int nchan, int ntime, int ntb, int npad,
+                                                      int64_t nthreads)
+{
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= nthreads) return;
+    const int ng = npad >> 2;
+    const int g = (int)(idx % ng);
+    const int64_t q = idx / ng;
+    const int tb = (int)(q % ntb);
+    const int f = (int)(q / ntb);
+    const int t0 = tb * SP_TB;
+    const bool live = 4 * g < nin;
+    uint32_t v[SP_TB];
+#pragma unroll
+    for (int t = 0; t < SP_TB; ++t)
+        v[t] = (live && t0 + t < ntime) ? ((const uint32_t *)(in + ((size_t)(t0 + t) * nchan + f) * nin))[g] : 0u;
+    uint32_t yr[4][8], yi[4][8];
+#pragma unroll
+    for (int qd = 0; qd < 8; ++qd) {
+        // 4 x 4 byte transpose: u[e] = input e at times 4 qd .. 4 qd + 3
+        const uint32_t *r = v + 4 * qd;
+        const uint32_t a_lo = __builtin_amdgcn_perm(r[1], r[0], 0x05010400u);
+        const uint32_t a_hi = __builtin_amdgcn_perm(r[1], r[0], 0x07030602u);
+        const uint32_t b_lo = __builtin_amdgcn_perm(r[3], r[2], 0x05010400u);
+        const uint32_t b_hi = __builtin_amdgcn_perm(r[3], r[2], 0x07030602u);
+        const uint32_t u[4] = {__builtin_amdgcn_perm(b_lo, a_lo, 0x05040100u),
+                               __builtin_amdgcn_perm(b_lo, a_lo, 0x07060302u),
+                               __builtin_amdgcn_perm(b_hi, a_hi, 0x05040100u),
+                               __builtin_amdgcn_perm(b_hi, a_hi, 0x07060302u)};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            yr[e][qd] = pack4x6(nibbles_to_e3m2((u[e] >> 4) & 0x0F0F0F0Fu));  // re: high nibble
+            yi[e][qd] = pack4x6(nibbles_to_e3m2(u[e] & 0x0F0F0F0Fu));         // im: low nibble
+        }
+    }
+    u32x4 *o = (u32x4 *)(work + (((size_t)f * ntb + tb) * npad + 4 * g) * F6_UNIT);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        uint32_t w[12];
+        groups_to_words(yr[e], w);
+        groups_to_words(yi[e], w + 6);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) o[3 * e + k] = (u32x4){w[4 * k], w[4 * k + 1], w[4 * k + 2], w[4 * k + 3]};
+    }
+}
+
+// Ring slot per block: the row segment (256 units), and for a rectangle the column segment
+// (128 units); NCOPY 1 KiB copies.
+template <int TRI>
+struct F6Geo {
+    static constexpr int ROWB = 256 * F6_UNIT, COLB = TRI ? 0 : 128 * F6_UNIT;
+    static constexpr int SLOT = ROWB + COLB, NCOPY = SLOT / 1024, LDS = F6_RING * SLOT;
+    static_assert(SLOT % 1024 == 0 && LDS <= 160 * 1024, "whole copies and LDS budget");
+};
+
+// Triangle block i (0..8) of SIMD s: the nine blocks below the diagonal in block rows s and
+// 7 - s, (s, 0 .. s) then (7 - s, 0 .. 7 - s).
+constexpr int f6_tri_br(int s, int i) { return i <= s ? s : 7 - s; }
+constexpr int f6_tri_bc(int s, int i) { return i <= s ? i : i - s - 1; }
+
+// Work of wave W (waves W and W + 4 share a SIMD): NB blocks (BR, BC: block row in the row
+// segment, block column in the column segment, which in a triangle is the same segment).
+// Rectangles: block rows {2 (W / 2), + 1} x columns {2 (W % 2), + 1}; triangles: the first
+// five of SIMD W % 4's nine blocks for W < 4, the last four for W >= 4.  DPW copies per
+// block (copies W, W + 8, ..).
+template <int TRI, int W>
+struct F6Wave {
+    static constexpr int NB = TRI ? (W < 4 ? 5 : 4) : 4;
+    static constexpr int br(int b) { return TRI ? f6_tri_br(W & 3, (W < 4 ? 0 : 5) + b) : 2 * (W >> 1) + (b >> 1); }
+    static constexpr int bc(int b) { return TRI ? f6_tri_bc(W & 3, (W < 4 ? 0 : 5) + b) : 2 * (W & 1) + (b & 1); }
+    static constexpr bool uses_row(int r)
+    {
+        for (int b = 0; b < NB; ++b)
+            if (br(b) == r) return true;
+        return false;
+    }
+    static constexpr bool uses_col(int c)
+    {
+        for (int b = 0; b < NB; ++b)
+            if (bc(b) == c) return true;
+        return false;
+    }
+    // plain fragment f: f < 8 block row f of the row segment, f >= 8 block f - 8 of the
+    // column segment (a triangle reads both roles from the row segment)
+    static constexpr int plain_of_col(int c) { return TRI ? c : 8 + c; }
+    static constexpr bool reads(int f) { return f < 8 ? (uses_row(f) || (TRI && uses_col(f))) : (!TRI && uses_col(f - 8)); }
+    // greedy pairing for the stores: block b starts a pair with b + 1 (same row, next column)
+    static constexpr int kind(int b)  // 2: pair start, 1: single, 0: second of a pair
+    {
+        int i = 0;
+        while (i < NB) {
+            const bool pr = i + 1 < NB && br(i) == br(i + 1) && bc(i + 1) == bc(i) + 1;
+            if (i == b) return pr ? 2 : 1;
+            if (pr && i + 1 == b) return 0;
+            i += pr ? 2 : 1;
+        }
+        return 0;
+    }
+    static constexpr int DPW = (F6Geo<TRI>::NCOPY - W + 7) / 8;
+};
+
+struct F6Frag {
+    uint32_t w[6];
+};
+
+typedef uint32_t f6_u32x2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(3))) f6_u32x2 f6_lds_u2;
+
+__device__ __forceinline__ void read_f6(uint32_t a, F6Frag &x)
+{
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const f6_u32x2 v = *(const f6_lds_u2 *)(uintptr_t)(a + 8 * k);
+        x.w[2 * k] = v[0];
+        x.w[2 * k + 1] = v[1];
+    }
+}
+
+// (re | im) -> (im | -re): the lane halves exchanged (one lane swap and one select per
+// word), then the sign bits of the second half's codes flipped (nm: zero in lanes 0..31).
+__device__ __forceinline__ void rotate_f6(const F6Frag &x, F6Frag &r, bool upper, const uint32_t (&nm)[3])
+{
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        uint32_t a = x.w[k], b = x.w[k];
+        lane_swap32(a, b);  // a = (lo, lo), b = (hi, hi)
+        r.w[k] = (upper ? a : b) ^ nm[k % 3];
+    }
+}
+
+__device__ __forceinline__ void mma_f6(f32x16 &c, const F6Frag &a, const F6Frag &b)
+{
+    const i32x8 av = {(int)a.w[0], (int)a.w[1], (int)a.w[2], (int)a.w[3], (int)a.w[4], (int)a.w[5], 0, 0};
+    const i32x8 bv = {(int)b.w[0], (int)b.w[1], (int)b.w[2], (int)b.w[3], (int)b.w[4], (int)b.w[5], 0, 0};
+    // formats 3/3: fp6 e3m2 for both operands (six words each); E8M0 scales 2^0
+    c = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, bv, c, 3, 3, 0, 127, 0, 127);
+}
+
+template <int TRI, int W>
+__device__ __forceinline__ void run_wave_f6(const XJob &p, int lane)
+{
+    using G = F6Geo<TRI>;
+    using S = F6Wave<TRI, W>;
+    constexpr int RING = F6_RING, DPW = S::DPW;
+    static_assert((RING - 2) * DPW < 64, "vmcnt range");
+    const uint32_t lds0 = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) uint8_t *)chan_lds;
+    const int ntb = (p.ntime + SP_TB - 1) / SP_TB;
+    const int npad = 256 * p.ntile_side;
+    // lane-half h reads word group h of its input's unit
+    const uint32_t lo = (uint32_t)((lane & 31) * F6_UNIT + 24 * (lane >> 5));
+    const bool upper = lane >= 32;
+    const uint32_t hm = upper ? 0xFFFFFFFFu : 0u;
+    const uint32_t nm[3] = {hm & 0x20820820u, hm & 0x08208208u, hm & 0x82082082u};  // sign bits 6k + 5
+
+    // descriptor of one segment of the block the cursor points at (nothing past the end)
+    auto desc = [&](const SCursor<TRI> &c, int first, int bytes) __attribute__((always_inline)) {
+        const int tb = (c.t0 / SP_TB) + c.blk;
+        const uint64_t base =
+            (uint64_t)p.work + ((uint64_t)((int64_t)c.f * ntb + tb) * (uint64_t)npad + (uint64_t)first) * F6_UNIT;
+        i32x4s r;
+        r[0] = __builtin_amdgcn_readfirstlane((int)(uint32_t)base);
+        r[1] = __builtin_amdgcn_readfirstlane((int)((uint32_t)(base >> 32) & 0xFFFFu));
+        r[2] = c.valid ? bytes : 0;
+        r[3] = 0x00020000;
+        return r;
+    };
+    auto issue = [&](const SCursor<TRI> &c, int slot) __attribute__((always_inline)) {
+        const uint32_t sb = lds0 + (uint32_t)(slot * G::SLOT);
+        const i32x4s dr = desc(c, c.seg_a, G::ROWB);
+        const i32x4s dcol = desc(c, TRI ? c.seg_a : c.seg_b, TRI ? G::ROWB : G::COLB);
+        static_for<DPW>([&](auto M) __attribute__((always_inline)) {
+            constexpr int k = W + 8 * decltype(M)::value;
+            if constexpr (k < 12) dma16(dr, sb + 1024 * k, (uint32_t)(1024 * k + 16 * lane));
+            else dma16(dcol, sb + 1024 * k, (uint32_t)(1024 * (k - 12) + 16 * lane));
+        });
+    };
+
+    f32x16 are[S::NB], aim[S::NB];
+#pragma unroll
+    for (int b = 0; b < S::NB; ++b) {
+        are[b] = (f32x16){};
+        aim[b] = (f32x16){};
+    }
+    F6Frag P[16], R[8];
+    auto block = [&](int slot) __attribute__((always_inline)) {
+        const uint32_t sb = lds0 + (uint32_t)(slot * G::SLOT);
+        static_for<16>([&](auto F) __attribute__((always_inline)) {
+            constexpr int f = decltype(F)::value;
+            if constexpr (S::reads(f))
+                read_f6(sb + (f < 8 ? 0u : (uint32_t)G::ROWB) + 32 * F6_UNIT * (f & 7) + lo, P[f]);
+        });
+        static_for<8>([&](auto RB) __attribute__((always_inline)) {
+            constexpr int r = decltype(RB)::value;
+            if constexpr (S::uses_row(r)) rotate_f6(P[r], R[r], upper, nm);
+        });
+        static_for<S::NB>([&](auto B) __attribute__((always_inline)) {
+            constexpr int b = decltype(B)::value;
+            constexpr int r = S::br(b), c = S::plain_of_col(S::bc(b));
+            mma_f6(are[b], P[r], P[c]);
+            mma_f6(aim[b], R[r], P[c]);
+        });
+    };
+    auto store = [&](const SCursor<TRI> &c) __attribute__((always_inline)) {
+        // opaque copies: keep the store masks from being hoisted out of the item loop
+        int nin = p.nin, npol = p.npol, accumulate = p.accumulate, l = lane;
+        asm volatile("" : "+s"(nin), "+s"(npol), "+s"(accumulate), "+v"(l));
+        const int cb = TRI ? c.seg_a : c.seg_b;
+        if (npol == 2 && !accumulate) {
+            static_for<S::NB>([&](auto B) __attribute__((always_inline)) {
+                constexpr int b = decltype(B)::value;
+                if constexpr (S::kind(b) == 2)
+                    store_pair<ACC_F8>(p.out, nin, c.f, c.seg_a + 32 * S::br(b), cb + 32 * S::bc(b), l, are[b], aim[b],
+                                       are[b + 1], aim[b + 1]);
+                else if constexpr (S::kind(b) == 1)
+                    store_block<ACC_F8>(p.out, nin, npol, accumulate, c.f, c.seg_a + 32 * S::br(b),
+                                        cb + 32 * S::bc(b), l, are[b], aim[b]);
+            });
+        } else {
+            static_for<S::NB>([&](auto B) __attribute__((always_inline)) {
+                constexpr int b = decltype(B)::value;
+                store_block<ACC_F8>(p.out, nin, npol, accumulate, c.f, c.seg_a + 32 * S::br(b), cb + 32 * S::bc(b),
+                                    l, are[b], aim[b]);
+            });
+        }
+    };
+
+    SCursor<TRI> dc, cc;
+    dc.init(p);
+    cc.init(p);
+#pragma unroll
+    for (int d = 0; d < RING - 1; ++d) {
+        issue(dc, d);
+        dc.next(p);
+    }
+    wait_vm<(RING - 2) * DPW>();
+    int slot = 0, ready = 1;
+    // items, each a loop over its blocks, then its stores.  A block: its copies complete
+    // (own, then everyone's: the barrier also means that every wave has issued the MFMAs of
+    // the previous block, so that block's slot is free); the copy of block + RING - 1 into
+    // that slot; this block's fragments and MFMAs.
+    while (cc.valid) {
+        do {
+            if (ready == 0) wait_vm<(RING - 2) * DPW>();
+            else --ready;
+            __syncthreads();
+            issue(dc, slot == 0 ? RING - 1 : slot - 1);
+            dc.next(p);
+            block(slot);
+            slot = slot == RING - 1 ? 0 : slot + 1;
+        } while (++cc.blk < cc.nblk);
+        wait_vm<0>();
+        ready = RING - 1;
+        store(cc);
+#pragma unroll
+        for (int b = 0; b < S::NB; ++b) {
+            are[b] = (f32x16){};
+            aim[b] = (f32x16){};
+        }
+        cc.set(p, cc.step + 1);
+    }
+    // no copy into LDS may outlive the workgroup
+    wait_vm<0>();
+}
+
+template <int TRI>
+__global__ __launch_bounds__(F6_CT, 1) void xeng_super_f6_kernel(XJob p)
+{
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    switch (wave) {
+    case 0: run_wave_f6<TRI, 0>(p, lane); break;
+    case 1: run_wave_f6<TRI, 1>(p, lane); break;
+    case 2: run_wave_f6<TRI, 2>(p, lane); break;
+    case 3: run_wave_f6<TRI, 3>(p, lane); break;
+    case 4: run_wave_f6<TRI, 4>(p, lane); break;
+    case 5: run_wave_f6<TRI, 5>(p, lane); break;
+    case 6: run_wave_f6<TRI, 6>(p, lane); break;
+    default: run_wave_f6<TRI, 7>(p, lane); break;
+    }
+}
+
+template <int TRI>
+int launch_super_f6_kind(XJob job, int cus, hipStream_t stream)
+{
+    constexpr int LDS = F6Geo<TRI>::LDS;
+    if (int e = allow_lds_on_device<xeng_super_f6_kernel<TRI>>(LDS)) return e;
+    const int ns = job.ntile_side;
+    job.nitems = (int64_t)job.nwindows * job.nchan * (TRI ? ns : ns * (ns - 1));
+    job.grid = job.nitems < cus ? job.nitems : cus;
+    if (job.grid <= 0) return 0;
+    hipLaunchKernelGGL((xeng_super_f6_kernel<TRI>), dim3((unsigned)job.grid), dim3(F6_CT), LDS, stream, job);
+    return (int)hipGetLastError();
+}
+
 }  // namespace
 
 // Both launches of a super-tiled job (triangles, then rectangles); each sets its own item
 // count and grid (at most one workgroup per compute unit, `cus`).
 int launch_super(const XJob &job, int acc, int in_fmt, int cus, hipStream_t stream)
 {
+    if (in_fmt == IN_CI4 && acc == ACC_F6) {
+        // the pre-pass into the unit workspace, then triangles and rectangles
+        if (!job.work || job.nin % 4 != 0) return (int)hipErrorInvalidValue;
+        const int npad = 256 * job.ntile_side, ntb = (job.ntime + SP_TB - 1) / SP_TB;
+        const int64_t nth = (int64_t)job.nchan * ntb * (npad / 4);
+        if (nth > 0) {
+            hipLaunchKernelGGL(f6_pack_kernel, dim3((unsigned)((nth + 255) / 256)), dim3(256), 0, stream,
+                               (const uint8_t *)job.in, (uint8_t *)job.work, job.nin, job.nchan, job.ntime, ntb,
+                               npad, nth);
+            if (int e = (int)hipGetLastError()) return e;
+        }
+        if (int e = launch_super_f6_kind<1>(job, cus, stream)) return e;
+        return launch_super_f6_kind<0>(job, cus, stream);
+    }
     if (in_fmt == IN_CI4 && acc == ACC_I8) return launch_super_pair<ACC_I8, IN_CI4>(job, cus, stream);
     if (in_fmt == IN_CI4 && acc == ACC_F8) return launch_super_pair<ACC_F8, IN_CI4>(job, cus, stream);
     if (in_fmt == IN_CI8 && acc == ACC_I8) return launch_super_pair<ACC_I8, IN_CI8>(job, cus, stream);

@@ -346,14 +346,24 @@ def test_fp32_matrix_core_path_plans():
 
 def test_fp6_path_plans():
     """fp6 e3m2 holds the integers of [-8, 8]: CI4 always, CI8 only with a declared bound of
-    at most 8; fp32 windows; the tiled kernel."""
+    at most 8; fp32 windows; super-tiles for 4-bit samples above 256 inputs, else the tiled
+    kernel."""
     assert X.xcorr_window_limit(X.IN_CI4, X.ACC_F6E3M2_MMA_F32, 8) == 131072
     p = X.xcorr_plan(512, 2, 256, 4096, X.IN_CI4, X.ACC_F6E3M2_MMA_F32, 0)
-    assert p["tile"] == 128 and p["out_dtype"] == X.OUT_C64 and p["max_abs"] == 8
+    assert p["tile"] == 512 and p["out_dtype"] == X.OUT_C64 and p["max_abs"] == 8
     assert X.xcorr_plan(8, 2, 1, 10, X.IN_CI8, X.ACC_F6E3M2_MMA_F32, 8)["out_dtype"] == X.OUT_C64
     with pytest.raises(X.XcorrError) as e:
         X.xcorr_plan(8, 2, 1, 10, X.IN_CI8, X.ACC_F6E3M2_MMA_F32, 9)
     assert e.value.code == X.ERR_UNSUPPORTED
-    for tile in (256, 512):
+    with pytest.raises(X.XcorrError):
+        X.xcorr_plan(512, 2, 4, 100, X.IN_CI4, X.ACC_F6E3M2_MMA_F32, 0, 256)
+    # super-tiles on request (4-bit samples): windows must start on whole 32-sample blocks,
+    # and 8-bit samples stay on the tiled kernel
+    q = X.xcorr_plan(512, 2, 4, 100, X.IN_CI4, X.ACC_F6E3M2_MMA_F32, 0, 512)
+    assert q["tile"] == 512 and q["ntile_side"] == 4 and q["tiles_per_chan"] == 16
+    assert X.xcorr_plan(512, 2, 4, 100, X.IN_CI4, X.ACC_F6E3M2_MMA_F32, 0, 512, 64)["nwindows"] == 2
+    for bad in ((X.IN_CI4, 48), (X.IN_CI4, 50)):
         with pytest.raises(X.XcorrError):
-            X.xcorr_plan(512, 2, 4, 100, X.IN_CI4, X.ACC_F6E3M2_MMA_F32, 0, tile)
+            X.xcorr_plan(512, 2, 4, 100, bad[0], X.ACC_F6E3M2_MMA_F32, 0, 512, bad[1])
+    with pytest.raises(X.XcorrError):
+        X.xcorr_plan(512, 2, 4, 100, X.IN_CI8, X.ACC_F6E3M2_MMA_F32, 8, 512)

@@ -69,7 +69,7 @@ def test_n1024_ci4_full_size(oracle_mod):
     for acc in ("i8", "f8", "f6"):
         say("full size 1024 inputs", acc)
         c = X.Correlator(ns, npol, F, T, "ci4", acc)
-        assert c.tile == (128 if acc == "f6" else 512)
+        assert c.tile == 512
         out = c.run(x)
         torch.cuda.synchronize()
         _sampled(oracle_mod, out, want, chans, f"n1024/{acc}")

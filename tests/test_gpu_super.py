@@ -1,6 +1,7 @@
-"""GPU parity of the super-tiled kernel (tile 512: 4-bit samples on the int8 or fp8 matrix
-cores, each channel cut into 256-input triangles and 256 x 128 rectangles, operands widened
-in LDS to 8 x the samples as int8, or to fp8 e4m3) against the oracle, bit for bit."""
+"""GPU parity of the super-tiled kernel (tile 512: 4-bit samples on the int8, fp8 or fp6
+matrix cores, each channel cut into 256-input triangles and 256 x 128 rectangles, operands
+widened in LDS to 8 x the samples as int8, or to fp8 e4m3; fp6 e3m2 units made by a
+pre-pass) against the oracle, bit for bit."""
 
 from __future__ import annotations
 
@@ -32,7 +33,7 @@ def _check(got, want, label):
     assert np.array_equal(g, want), label
 
 
-ACCS = ["i8", "f8"]
+ACCS = ["i8", "f8", "f6"]
 
 
 @pytest.mark.parametrize("acc", ACCS)
@@ -101,6 +102,43 @@ def test_super_f8_windows(oracle_mod):
     full, ot = run_xeng(packed, ns, npol, "ci4", "f8", tile=512)
     assert ot == X.OUT_C128
     _check(full, oracle_mod.xcorr(packed, ns, npol, fmt=oracle_mod.CI4), "super-f8-windows")
+
+
+def test_super_f6_windows(oracle_mod):
+    """fp6 super-tiles with two fp32 windows summed into fp64 totals (the windows start on
+    whole 32-sample blocks of the pre-pass's units), against the oracle."""
+    from paper_1107_4264_amd import xcorr as X
+
+    ns, npol, F, T = 136, 2, 1, 131072 + 300
+    p = X.xcorr_plan(ns, npol, F, T, X.IN_CI4, X.ACC_F6E3M2_MMA_F32, 0, 512)
+    assert p["nwindows"] == 2 and p["out_dtype"] == X.OUT_C128 and p["window"] % 32 == 0
+    packed = synth.pack_ci4(synth.voltages_np(synth.SEED_BASE + 67, T, F, ns * npol, ("uniform", -8, 7)))
+    say("super f6 windows", T)
+    full, ot = run_xeng(packed, ns, npol, "ci4", "f6", tile=512)
+    assert ot == X.OUT_C128
+    _check(full, oracle_mod.xcorr(packed, ns, npol, fmt=oracle_mod.CI4), "super-f6-windows")
+
+
+def test_super_f6_forced_windows(oracle_mod):
+    """Forced windows of whole blocks (96 samples) run on fp6 super-tiles; a window that
+    does not start on a block (100 samples) is refused for tile 512."""
+    from paper_1107_4264_amd import xcorr as X
+
+    ns, npol, F, T = 136, 2, 2, 300
+    p = X.xcorr_plan(ns, npol, F, T, X.IN_CI4, X.ACC_F6E3M2_MMA_F32, 0, 512, window=96)
+    assert p["tile"] == 512 and p["nwindows"] == 4
+    with pytest.raises(Exception):
+        X.xcorr_plan(ns, npol, F, T, X.IN_CI4, X.ACC_F6E3M2_MMA_F32, 0, 512, window=100)
+    packed = synth.pack_ci4(synth.voltages_np(synth.SEED_BASE + 68, T, F, ns * npol, ("uniform", -8, 7)))
+    c = X.Correlator(ns, npol, F, T, "ci4", "f6", tile=512, window=96)
+    import torch
+
+    from tests.gpu_util import device
+
+    out = c.run(torch.from_numpy(packed).to(device()))
+    torch.cuda.synchronize()
+    _check(out.cpu().numpy(), oracle_mod.xcorr(packed, ns, npol, fmt=oracle_mod.CI4), "super-f6-forced")
+    c.close()
 
 
 def test_super_stream_accumulates(oracle_mod):
@@ -191,7 +229,8 @@ def test_super_ci8_windows(oracle_mod):
 
 
 
-@pytest.mark.parametrize("fmt_acc", [("ci4", "i8"), ("ci4", "f8"), ("ci8", "i8")], ids=lambda t: "-".join(t))
+@pytest.mark.parametrize("fmt_acc", [("ci4", "i8"), ("ci4", "f8"), ("ci4", "f6"), ("ci8", "i8")],
+                         ids=lambda t: "-".join(t))
 @pytest.mark.parametrize("shape", [(136, 2, 2, 45), (200, 2, 2, 37), (392, 2, 1, 33), (304, 1, 2, 40)],
                          ids=lambda s: "x".join(map(str, s)))
 def test_super_ragged(oracle_mod, fmt_acc, shape):

@@ -141,22 +141,23 @@ def constant_worst_ci4(T, F, nin):
     return np.broadcast_to(row, (T, F, nin)).copy()
 
 
-def test_fp6_window_bound_ci4(oracle_mod):
+@pytest.mark.parametrize("tile", [64, 512])
+def test_fp6_window_bound_ci4(oracle_mod, tile):
     """4-bit samples at -8 - 8i on the fp6 path: T = 131072 (one fp32 window, c64) and
-    T = 131073 (two windows, c128)."""
+    T = 131073 (two windows, c128); 64-tiles and super-tiles (units from the pre-pass)."""
     from paper_1107_4264_amd import xcorr as X
 
-    ns, npol, F = 4, 2, 1
+    ns, npol, F = (4, 2, 1) if tile == 64 else (136, 2, 1)
     lim = X.xcorr_window_limit(X.IN_CI4, X.ACC_F6E3M2_MMA_F32, 8)
     assert lim == 131072
     for T, want_type in ((lim, X.OUT_C64), (lim + 1, X.OUT_C128)):
         x = constant_worst_ci4(T, F, ns * npol)
-        say("fp6 window bound", T)
-        got, ot, _ = _run(x, ns, npol, "ci4", "f6")
-        assert ot == want_type
+        say("fp6 window bound", tile, T)
+        got, ot, t = _run(x, ns, npol, "ci4", "f6", tile=tile)
+        assert ot == want_type and t == tile
         want = oracle_mod.xcorr(x, ns, npol, fmt=oracle_mod.CI4)
         assert int(want[..., 0].max()) == T * 128
-        _check(got, want, f"fp6-bound/{T}")
+        _check(got, want, f"fp6-bound/{tile}/{T}")
 
 
 @pytest.mark.parametrize("tile", [64, 512])
@@ -229,6 +230,7 @@ CASES = [
     ("ci4", "i8", 70, 1, 128),
     ("ci8", "f32m", 45, 2, 128),   # fp32 matrix cores
     ("ci4", "f6", 70, 2, 128),     # fp6 e3m2
+    ("ci4", "f6", 136, 2, 512),    # fp6 super-tiles (windows of whole blocks only)
     ("ci8", "f6", 33, 2, 64),
 ]
 
@@ -250,6 +252,11 @@ def test_requested_windows_match_oracle(oracle_mod, case, window):
         x = synth.voltages_np(synth.SEED_BASE + 91 + ns + window, T, F, ns * npol, dist)
         want = oracle_mod.xcorr(x, ns, npol)
     say("requested windows", case, window)
+    if acc == "f6" and tile == 512 and window % 32:
+        # fp6 super-tiles take windows of whole 32-sample blocks only: refused
+        with pytest.raises(X.XcorrError):
+            _run(x, ns, npol, fmt, acc, tile=tile, window=window)
+        return
     # 8-bit samples on the fp8 path need a declared bound of at most 16
     ma = low_max_abs(acc) if fmt == "ci8" else None
     got, ot, t = _run(x, ns, npol, fmt, acc, tile=tile, window=window, max_abs=ma)
