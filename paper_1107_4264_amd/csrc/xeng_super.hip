@@ -513,58 +513,57 @@ int launch_super_pair(const XJob &job, int cus, hipStream_t stream)
 // 4-bit samples on fp6 e3m2 operands (three exponent bits of bias 3, two mantissa bits:
 // every integer of [-8, 8] is exact) for the scaled f8f6f4 32x32x64 MFMA, at twice the
 // fp8 rate.  A pre-pass converts each (channel, block of 32 samples, input) once into a
-// 48-byte unit: the 32 real parts as e3m2 codes (six words, code k at bits 6k .. 6k + 5),
-// then the 32 imaginary parts.  Lane-half h of a fragment reads word group h of its
-// input's unit, so an MFMA of two plain fragments sums re_i re_j + im_i im_j over the
-// block (the real part of Eq. 4), and one whose row fragment is read with its halves
+// 48-byte unit: the 32 real parts as e3m2 codes (six words, code k at bits 6k .. 6k + 5,
+// in sample order) and the 32 imaginary parts.  Lane-half h of a fragment reads half h
+// of its input's unit, so an MFMA of two plain fragments sums re_i re_j + im_i im_j over
+// the block (the real part of Eq. 4), and one whose row fragment has its lane halves
 // exchanged and the second half negated, (im_i, -re_i), sums im_i re_j - re_i im_j (the
 // imaginary part).  Units are stored [channel][block][input], the inputs padded with zeros
 // to whole super-rows and the last block's samples past ntime zero, so that a piece copies
 // contiguous segments (12 KiB for 256 row inputs, 6 KiB for 128 column inputs) straight
-// into LDS: the main kernel converts nothing.  Four waves, one per SIMD: in a rectangle
-// wave w computes block rows {2w, 2w + 1} x the four column blocks, in a triangle block
-// rows {w, 7 - w} (nine blocks below the diagonal); the fragments of the next block are
-// read during the MFMAs of this one.
+// into LDS: the main kernel converts nothing.  Eight waves, two per SIMD, with 2 x 2
+// blocks each in a rectangle and four or five blocks of a SIMD's nine in a triangle.
+// Measured and dropped: four waves with 2 x 4 blocks (their 256 accumulator registers
+// spill), the real halves of 32 inputs stored apart from their imaginary halves (24-byte
+// lane strides in LDS) together with the next block's fragments read during this block's
+// MFMAs (1.2-1.5x slower: the compiler keeps a fragment set in scratch memory).
 
 constexpr int F6_UNIT = 48;    // bytes per input per block
 constexpr int F6_CT = 512;     // threads per workgroup: eight waves, two per SIMD
 constexpr int F6_RING = 6;     // blocks in the LDS ring
 
-// e3m2 codes of four signed 4-bit values (one per byte, low nibble): byte tables of the
-// values 0..7 and -8..-1 indexed by the low three bits, chosen by the sign bit of each
-// nibble (spread to a byte mask by a third permute).
-__device__ __forceinline__ uint32_t nibbles_to_e3m2(uint32_t n)
+// fp16 high bytes of four signed 4-bit values (one per byte, low nibble; the low bytes of
+// these fp16 values are zero): byte tables of the values 0..7 and -8..-1 indexed by the
+// low three bits, chosen by the sign bit of each nibble (spread to a byte mask by a third
+// permute).
+__device__ __forceinline__ uint32_t nibbles_to_f16hi(uint32_t n)
 {
     const uint32_t idx = n & 0x07070707u;
-    const uint32_t pos = __builtin_amdgcn_perm(0x17161514u, 0x12100C00u, idx);  // 0, 1, .., 7
-    const uint32_t neg = __builtin_amdgcn_perm(0x2C303234u, 0x35363738u, idx);  // -8, -7, .., -1
+    const uint32_t pos = __builtin_amdgcn_perm(0x47464544u, 0x42403C00u, idx);  // 0, 1, .., 7
+    const uint32_t neg = __builtin_amdgcn_perm(0xBCC0C2C4u, 0xC5C6C7C8u, idx);  // -8, -7, .., -1
     const uint32_t t = (n >> 3) & 0x01010101u;
     const uint32_t m = __builtin_amdgcn_perm(0u, 0x0000FF00u, t);
     return (neg & m) | (pos & ~m);
 }
 
-// Four 6-bit codes (one per byte) -> 24 bits, code k at bits 6k.
-__device__ __forceinline__ uint32_t pack4x6(uint32_t c)
+// 32 fp16 values (two per word, sample order) -> six words of e3m2 codes (gfx950's packed
+// conversion, scale 1; exact for the integers of [-8, 8]).
+__device__ __forceinline__ void f16x32_to_e3m2(const uint32_t (&h)[16], uint32_t *w)
 {
-    const uint32_t u = ((c >> 2) & 0x0FC00FC0u) | (c & 0x003F003Fu);
-    return ((u >> 4) & 0x00FFF000u) | (u & 0x00000FFFu);
-}
-
-// Eight 24-bit groups (samples 4q .. 4q + 3 in group q) -> the six words of 32 codes.
-__device__ __forceinline__ void groups_to_words(const uint32_t (&y)[8], uint32_t *w)
-{
+    typedef _Float16 h32 __attribute__((ext_vector_type(32)));
+    typedef uint32_t u32x16 __attribute__((ext_vector_type(16)));
+    u32x16 hv;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        w[3 * h] = y[4 * h] | (y[4 * h + 1] << 24);
-        w[3 * h + 1] = (y[4 * h + 1] >> 8) | (y[4 * h + 2] << 16);
-        w[3 * h + 2] = (y[4 * h + 2] >> 16) | (y[4 * h + 3] << 8);
-    }
+    for (int k = 0; k < 16; ++k) hv[k] = h[k];
+    const auto p = __builtin_amdgcn_cvt_scalef32_pk32_bf6_f16(__builtin_bit_cast(h32, hv), 1.0f);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) w[k] = p[k];
 }
 
 // Pre-pass.  One thread: four consecutive inputs (one word of 4-bit samples per time row)
-// of one block of 32 samples of one channel -> their four units.  Threads run over
-// (channel, block, input group), input groups fastest: a wave reads 256 consecutive bytes
-// of each time row and writes 12 KiB of consecutive units.
+// of one block of 32 samples of one channel -> their four units (192 consecutive bytes).
+// Threads run over (channel, block, input group of four), input groups fastest: a wave
+// reads 256 consecutive bytes of each time row and writes 12 KiB of consecutive units.
 __global__ __launch_bounds__(256) void f6_pack_kernel(const uint8_t *__restrict__ in, uint8_t *__restrict__ work,
                                                       int nin, int nchan, int ntime, int ntb, int npad,
                                                       int64_t nthreads)
@@ -582,33 +581,35 @@ __global__ __launch_bounds__(256) void f6_pack_kernel(const uint8_t *__restrict_
 #pragma unroll
     for (int t = 0; t < SP_TB; ++t)
         v[t] = (live && t0 + t < ntime) ? ((const uint32_t *)(in + ((size_t)(t0 + t) * nchan + f) * nin))[g] : 0u;
-    uint32_t yr[4][8], yi[4][8];
-#pragma unroll
-    for (int qd = 0; qd < 8; ++qd) {
-        // 4 x 4 byte transpose: u[e] = input e at times 4 qd .. 4 qd + 3
-        const uint32_t *r = v + 4 * qd;
-        const uint32_t a_lo = __builtin_amdgcn_perm(r[1], r[0], 0x05010400u);
-        const uint32_t a_hi = __builtin_amdgcn_perm(r[1], r[0], 0x07030602u);
-        const uint32_t b_lo = __builtin_amdgcn_perm(r[3], r[2], 0x05010400u);
-        const uint32_t b_hi = __builtin_amdgcn_perm(r[3], r[2], 0x07030602u);
-        const uint32_t u[4] = {__builtin_amdgcn_perm(b_lo, a_lo, 0x05040100u),
-                               __builtin_amdgcn_perm(b_lo, a_lo, 0x07060302u),
-                               __builtin_amdgcn_perm(b_hi, a_hi, 0x05040100u),
-                               __builtin_amdgcn_perm(b_hi, a_hi, 0x07060302u)};
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            yr[e][qd] = pack4x6(nibbles_to_e3m2((u[e] >> 4) & 0x0F0F0F0Fu));  // re: high nibble
-            yi[e][qd] = pack4x6(nibbles_to_e3m2(u[e] & 0x0F0F0F0Fu));         // im: low nibble
-        }
-    }
-    u32x4 *o = (u32x4 *)(work + (((size_t)f * ntb + tb) * npad + 4 * g) * F6_UNIT);
+    uint32_t wr[24], wi[24];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-        uint32_t w[12];
-        groups_to_words(yr[e], w);
-        groups_to_words(yi[e], w + 6);
+        // byte e of each time row (input 4g + e), four rows per word: (re, im) nibbles
+        const uint32_t sel = 0x0C0C0000u | ((uint32_t)(4 + e) << 8) | (uint32_t)e;
+        uint32_t hr[16], hm[16];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) o[3 * e + k] = (u32x4){w[4 * k], w[4 * k + 1], w[4 * k + 2], w[4 * k + 3]};
+        for (int qd = 0; qd < 8; ++qd) {
+            const uint32_t *r = v + 4 * qd;
+            const uint32_t u = __builtin_amdgcn_perm(__builtin_amdgcn_perm(r[3], r[2], sel),
+                                                     __builtin_amdgcn_perm(r[1], r[0], sel), 0x05040100u);
+            const uint32_t cr = nibbles_to_f16hi((u >> 4) & 0x0F0F0F0Fu);
+            const uint32_t cm = nibbles_to_f16hi(u & 0x0F0F0F0Fu);
+            hr[2 * qd] = __builtin_amdgcn_perm(0u, cr, 0x010C000Cu);
+            hr[2 * qd + 1] = __builtin_amdgcn_perm(0u, cr, 0x030C020Cu);
+            hm[2 * qd] = __builtin_amdgcn_perm(0u, cm, 0x010C000Cu);
+            hm[2 * qd + 1] = __builtin_amdgcn_perm(0u, cm, 0x030C020Cu);
+        }
+        f16x32_to_e3m2(hr, wr + 6 * e);
+        f16x32_to_e3m2(hm, wi + 6 * e);
+    }
+    // the four units, consecutive: real half, then imaginary half, of each input
+    u32x4 *o = (u32x4 *)(work + (((size_t)f * ntb + tb) * npad + 4 * (size_t)g) * F6_UNIT);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const uint32_t *a = wr + 6 * e, *b = wi + 6 * e;
+        o[3 * e] = (u32x4){a[0], a[1], a[2], a[3]};
+        o[3 * e + 1] = (u32x4){a[4], a[5], b[0], b[1]};
+        o[3 * e + 2] = (u32x4){b[2], b[3], b[4], b[5]};
     }
 }
 
