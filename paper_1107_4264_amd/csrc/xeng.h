@@ -47,8 +47,8 @@ struct XJob {
     void *work;           // fp6 super-tiles: the unit workspace (f6_work_bytes), else unused
 };
 
-// Bytes of the fp6 super-tiles' unit workspace: one 48-byte unit per (channel, block of 32
-// samples, input), the inputs padded to whole super-rows of 256.
+// Bytes of the fp6 super-tiles' workspace: 48 bytes (the e3m2 codes of 32 samples) per
+// (channel, block of 32 samples, input), the inputs padded to whole super-rows of 256.
 inline size_t f6_work_bytes(int nin, int nchan, int ntime)
 {
     const size_t npad = 256 * (size_t)((nin + 255) / 256), ntb = (size_t)((ntime + 31) / 32);

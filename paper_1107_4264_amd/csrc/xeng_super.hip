@@ -512,21 +512,23 @@ int launch_super_pair(const XJob &job, int cus, hipStream_t stream)
 //
 // 4-bit samples on fp6 e3m2 operands (three exponent bits of bias 3, two mantissa bits:
 // every integer of [-8, 8] is exact) for the scaled f8f6f4 32x32x64 MFMA, at twice the
-// fp8 rate.  A pre-pass converts each (channel, block of 32 samples, input) once into a
-// 48-byte unit: the 32 real parts as e3m2 codes (six words, code k at bits 6k .. 6k + 5,
-// in sample order) and the 32 imaginary parts.  Lane-half h of a fragment reads half h
-// of its input's unit, so an MFMA of two plain fragments sums re_i re_j + im_i im_j over
+// fp8 rate.  A pre-pass converts each (channel, block of 32 samples, input) once into 48
+// bytes: the 32 real parts as e3m2 codes (six words, code k at bits 6k .. 6k + 5, in
+// sample order) and the 32 imaginary parts.  Lane-half h of a fragment reads half h of its
+// input's codes, so an MFMA of two plain fragments sums re_i re_j + im_i im_j over
 // the block (the real part of Eq. 4), and one whose row fragment has its lane halves
 // exchanged and the second half negated, (im_i, -re_i), sums im_i re_j - re_i im_j (the
-// imaginary part).  Units are stored [channel][block][input], the inputs padded with zeros
-// to whole super-rows and the last block's samples past ntime zero, so that a piece copies
-// contiguous segments (12 KiB for 256 row inputs, 6 KiB for 128 column inputs) straight
-// into LDS: the main kernel converts nothing.  Eight waves, two per SIMD, with 2 x 2
-// blocks each in a rectangle and four or five blocks of a SIMD's nine in a triangle.
+// imaginary part).  The halves of 32 consecutive inputs form a 1536-byte group: their 32
+// real halves (24 bytes each), then their 32 imaginary halves, so that the lanes of a
+// fragment read at 24-byte strides (fewer LDS bank conflicts than whole 48-byte units:
+// 2-3 % faster).  Groups are stored [channel][block][input / 32], the inputs padded with
+// zeros to whole super-rows and the last block's samples past ntime zero, so that a piece
+// copies contiguous segments (12 KiB for 256 row inputs, 6 KiB for 128 column inputs)
+// straight into LDS: the main kernel converts nothing.  Eight waves, two per SIMD, with
+// 2 x 2 blocks each in a rectangle and four or five blocks of a SIMD's nine in a triangle.
 // Measured and dropped: four waves with 2 x 4 blocks (their 256 accumulator registers
-// spill), the real halves of 32 inputs stored apart from their imaginary halves (24-byte
-// lane strides in LDS) together with the next block's fragments read during this block's
-// MFMAs (1.2-1.5x slower: the compiler keeps a fragment set in scratch memory).
+// spill), and the next block's fragments read during this block's MFMAs (1.2-1.5x
+// slower: the compiler keeps a fragment set in scratch memory).
 
 constexpr int F6_UNIT = 48;    // bytes per input per block
 constexpr int F6_CT = 512;     // threads per workgroup: eight waves, two per SIMD
@@ -561,15 +563,15 @@ __device__ __forceinline__ void f16x32_to_e3m2(const uint32_t (&h)[16], uint32_t
 }
 
 // Pre-pass.  One thread: four consecutive inputs (one word of 4-bit samples per time row)
-// of one block of 32 samples of one channel -> their four units (192 consecutive bytes).
-// Threads run over (channel, block, input group of four), input groups fastest: a wave
-// reads 256 consecutive bytes of each time row and writes 12 KiB of consecutive units.
+// of one block of 32 samples of one channel -> their real and imaginary halves.  Threads
+// run over (channel, block, input group of four), input groups fastest: a wave reads 256
+// consecutive bytes of each time row and writes 12 KiB of consecutive groups.
 __global__ __launch_bounds__(256) void f6_pack_kernel(const uint8_t *__restrict__ in, uint8_t *__restrict__ work,
                                                       int nin, int nchan, int ntime, int ntb, int npad,
                                                       int64_t nthreads)
 {
     const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (idx >= nthreads) return;
+    if (idx >= nthreads) return;  // whole waves: nthreads is a multiple of 64
     const int ng = npad >> 2;
     const int g = (int)(idx % ng);
     const int64_t q = idx / ng;
@@ -602,19 +604,30 @@ __global__ __launch_bounds__(256) void f6_pack_kernel(const uint8_t *__restrict_
         f16x32_to_e3m2(hr, wr + 6 * e);
         f16x32_to_e3m2(hm, wi + 6 * e);
     }
-    // the four units, consecutive: real half, then imaginary half, of each input
-    u32x4 *o = (u32x4 *)(work + (((size_t)f * ntb + tb) * npad + 4 * (size_t)g) * F6_UNIT);
+    // The wave's 256 inputs are eight groups of 32 (12 KiB); the lanes' halves pass through
+    // LDS so that store k writes the wave's 16-byte chunks 64 k .. 64 k + 63 (1 KiB of
+    // consecutive bytes).  A wave's 64 input groups never straddle a (channel, block):
+    // npad / 4 is a multiple of 64.
+    __shared__ u32x4 stage[4][64 * 12];
+    const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+    // lane ln's inputs are 4 (ln % 8) .. + 3 of the wave's 32-input group ln / 8: their real
+    // halves are chunks 96 (ln / 8) + 6 (ln % 8) + 0..5, their imaginary halves 48 further
+    const int c0 = 96 * (ln >> 3) + 6 * (ln & 7);
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        const uint32_t *a = wr + 6 * e, *b = wi + 6 * e;
-        o[3 * e] = (u32x4){a[0], a[1], a[2], a[3]};
-        o[3 * e + 1] = (u32x4){a[4], a[5], b[0], b[1]};
-        o[3 * e + 2] = (u32x4){b[2], b[3], b[4], b[5]};
+    for (int k = 0; k < 6; ++k) {
+        stage[wv][c0 + k] = (u32x4){wr[4 * k], wr[4 * k + 1], wr[4 * k + 2], wr[4 * k + 3]};
+        stage[wv][c0 + 48 + k] = (u32x4){wi[4 * k], wi[4 * k + 1], wi[4 * k + 2], wi[4 * k + 3]};
     }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    u32x4 *o = (u32x4 *)(work + (((size_t)f * ntb + tb) * npad + 4 * (size_t)(g - ln)) * F6_UNIT);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) o[64 * k + ln] = stage[wv][64 * k + ln];
 }
 
-// Ring slot per block: the row segment (256 units), and for a rectangle the column segment
-// (128 units); NCOPY 1 KiB copies.
+// Ring slot per block: the row segment (256 inputs, 48 bytes each), and for a rectangle the
+// column segment (128 inputs); NCOPY 1 KiB copies.
 template <int TRI>
 struct F6Geo {
     static constexpr int ROWB = 256 * F6_UNIT, COLB = TRI ? 0 : 128 * F6_UNIT;
@@ -715,8 +728,9 @@ __device__ __forceinline__ void run_wave_f6(const XJob &p, int lane)
     const uint32_t lds0 = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) uint8_t *)chan_lds;
     const int ntb = (p.ntime + SP_TB - 1) / SP_TB;
     const int npad = 256 * p.ntile_side;
-    // lane-half h reads word group h of its input's unit
-    const uint32_t lo = (uint32_t)((lane & 31) * F6_UNIT + 24 * (lane >> 5));
+    // lane-half h reads the real (h = 0) or imaginary (h = 1) half of its input in the
+    // 32-input group of the fragment's block
+    const uint32_t lo = (uint32_t)(768 * (lane >> 5) + 24 * (lane & 31));
     const bool upper = lane >= 32;
     const uint32_t hm = upper ? 0xFFFFFFFFu : 0u;
     const uint32_t nm[3] = {hm & 0x20820820u, hm & 0x08208208u, hm & 0x82082082u};  // sign bits 6k + 5
