@@ -527,8 +527,8 @@ int launch_super_pair(const XJob &job, int cus, hipStream_t stream)
 // straight into LDS: the main kernel converts nothing.  Eight waves, two per SIMD, with
 // 2 x 2 blocks each in a rectangle and four or five blocks of a SIMD's nine in a triangle.
 // Measured and dropped: four waves with 2 x 4 blocks (their 256 accumulator registers
-// spill), and the next block's fragments read during this block's MFMAs (1.2-1.5x
-// slower: the compiler keeps a fragment set in scratch memory).
+// spill), and the next block's fragments read during this block's MFMAs (no faster: the
+// pieces are bound by LDS bandwidth, not by the reads' latency).
 
 constexpr int F6_UNIT = 48;    // bytes per input per block
 constexpr int F6_CT = 512;     // threads per workgroup: eight waves, two per SIMD
