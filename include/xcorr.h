@@ -179,7 +179,9 @@ int xcorr_get_staging(const xcorr_handle_t *h);
  * instead of the four five-block waves;
  * super-tiles (tile 512) 0..3 — bit 0 uses a three-block instead of a four-block ring, bit 1
  * stages the rectangles' column operands also in rotated (-im, re) form, so that no wave
- * rotates a fragment (fp6 super-tiles: 0 only); the other kernels have variant 0 only.  XCORR_ERR_INVALID_ARG outside that range.  Same
+ * rotates a fragment (fp6 super-tiles: 0..1 — variant 0 reads the rotated row fragments
+ * from LDS, variant 1 exchanges the lane halves of the plain ones in registers); the other
+ * kernels have variant 0 only.  XCORR_ERR_INVALID_ARG outside that range.  Same
  * visibilities for every variant. */
 int xcorr_set_variant(xcorr_handle_t *h, int variant);
 int xcorr_get_variant(const xcorr_handle_t *h);

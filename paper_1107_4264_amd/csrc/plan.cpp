@@ -122,7 +122,7 @@ int kernel_variants(int tile, int acc)
 {
     if (acc == ACC_F32_CMAC) return 1;
     if (tile == CHAN_TILE) return acc == ACC_F16 ? 8 : 4;
-    if (tile == SUPER_TILE) return acc == ACC_F6 ? 1 : 4;
+    if (tile == SUPER_TILE) return acc == ACC_F6 ? 2 : 4;
     return 1;
 }
 
@@ -245,7 +245,7 @@ int make_plan(int nstation, int npol, int nchan, int ntime, int in_fmt, int acc,
     p.tile = tile;
     if (variant < 0 || variant >= kernel_variants(tile, acc)) {
         *err = "kernel variant out of range for the kernel shape (whole channel 0..3, fp16 0..7, super-tiles 0..3, fp6 "
-                "super-tiles and others 0)";
+                "super-tiles 0..1, others 0)";
         return XCORR_ERR_INVALID_ARG;
     }
     p.variant = variant;

@@ -126,6 +126,26 @@ def test_super_variant(oracle_mod, fmt_acc, shape, variant):
     _check(got, want, f"super-variant/{fmt}/{acc}/{shape}")
 
 
+@pytest.mark.parametrize("shape", [(256, 2, 2, 100), (200, 2, 2, 37), (136, 2, 3, 70), (512, 1, 2, 33)],
+                         ids=lambda s: "x".join(map(str, s)))
+def test_super_f6_variant(oracle_mod, shape):
+    """fp6 super-tiles, variant 1: the rotated row fragments made by exchanging the lane
+    halves of the plain ones in registers (variant 0 reads them from LDS, the other half
+    with its sign bits flipped); only 0..1 exist."""
+    from paper_1107_4264_amd import xcorr as X
+
+    ns, npol, F, T = shape
+    x = synth.pack_ci4(synth.voltages_np(5400 + ns, T, F, ns * npol, ("uniform", -8, 7)))
+    say("super f6 variant", shape)
+    got, sh = _run(x, ns, npol, "ci4", "f6", tile=512, variant=1)
+    assert sh == (512, 0, 1)
+    _check(got, oracle_mod.xcorr(x, ns, npol, fmt=oracle_mod.CI4), f"super-f6-variant/{shape}")
+    c = X.Correlator(ns, npol, F, T, "ci4", "f6", tile=512)
+    with pytest.raises(X.XcorrError):
+        X.xcorr_set_variant(c.h, 2)
+    c.close()
+
+
 @pytest.mark.parametrize("variant", [4, 5, 6, 7])
 @pytest.mark.parametrize("shape", [(128, 2, 5, 1000), (100, 2, 3, 257), (256, 1, 2, 130)],
                          ids=lambda s: "x".join(map(str, s)))
