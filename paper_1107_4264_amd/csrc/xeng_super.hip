@@ -740,22 +740,31 @@ __device__ __forceinline__ void run_wave_f6(const XJob &p, int lane)
     const uint32_t hm = upper ? 0xFFFFFFFFu : 0u;
     const uint32_t nm[3] = {hm & 0x20820820u, hm & 0x08208208u, hm & 0x82082082u};  // sign bits 6k + 5
 
-    // descriptor of one segment of the block the cursor points at (nothing past the end)
-    auto desc = [&](const SCursor<TRI> &c, int first, int bytes) __attribute__((always_inline)) {
+    // address of input 0 of the block the cursor points at; within an item it advances by
+    // one block of groups per block (recomputed only at a new item)
+    const uint64_t blk_bytes = (uint64_t)npad * F6_UNIT;
+    auto block_base_f6 = [&](const SCursor<TRI> &c) __attribute__((always_inline)) {
         const int tb = (c.t0 / SP_TB) + c.blk;
-        const uint64_t base =
-            (uint64_t)p.work + ((uint64_t)((int64_t)c.f * ntb + tb) * (uint64_t)npad + (uint64_t)first) * F6_UNIT;
+        return (uint64_t)p.work + (uint64_t)((int64_t)c.f * ntb + tb) * blk_bytes;
+    };
+    auto advance = [&](SCursor<TRI> &c, uint64_t &bbase) __attribute__((always_inline)) {
+        c.next(p);
+        bbase = c.blk == 0 ? block_base_f6(c) : bbase + blk_bytes;
+    };
+    // descriptor of one segment of that block (nothing past the end)
+    auto desc = [&](uint64_t bbase, bool valid, int first, int bytes) __attribute__((always_inline)) {
+        const uint64_t base = bbase + (uint64_t)(uint32_t)(first * F6_UNIT);
         i32x4s r;
         r[0] = __builtin_amdgcn_readfirstlane((int)(uint32_t)base);
         r[1] = __builtin_amdgcn_readfirstlane((int)((uint32_t)(base >> 32) & 0xFFFFu));
-        r[2] = c.valid ? bytes : 0;
+        r[2] = valid ? bytes : 0;
         r[3] = 0x00020000;
         return r;
     };
-    auto issue = [&](const SCursor<TRI> &c, int slot) __attribute__((always_inline)) {
+    auto issue = [&](const SCursor<TRI> &c, uint64_t bbase, int slot) __attribute__((always_inline)) {
         const uint32_t sb = lds0 + (uint32_t)(slot * G::SLOT);
-        const i32x4s dr = desc(c, c.seg_a, G::ROWB);
-        const i32x4s dcol = desc(c, TRI ? c.seg_a : c.seg_b, TRI ? G::ROWB : G::COLB);
+        const i32x4s dr = desc(bbase, c.valid, c.seg_a, G::ROWB);
+        const i32x4s dcol = desc(bbase, c.valid, TRI ? c.seg_a : c.seg_b, TRI ? G::ROWB : G::COLB);
         static_for<DPW>([&](auto M) __attribute__((always_inline)) {
             constexpr int k = W + 8 * decltype(M)::value;
             if constexpr (k < 12) dma16(dr, sb + 1024 * k, (uint32_t)(1024 * k + 16 * lane));
@@ -823,10 +832,11 @@ __device__ __forceinline__ void run_wave_f6(const XJob &p, int lane)
     SCursor<TRI> dc, cc;
     dc.init(p);
     cc.init(p);
+    uint64_t dbase = block_base_f6(dc);
 #pragma unroll
     for (int d = 0; d < RING - 1; ++d) {
-        issue(dc, d);
-        dc.next(p);
+        issue(dc, dbase, d);
+        advance(dc, dbase);
     }
     wait_vm<(RING - 2) * DPW>();
     int slot = 0, ready = 1;
@@ -839,8 +849,8 @@ __device__ __forceinline__ void run_wave_f6(const XJob &p, int lane)
             if (ready == 0) wait_vm<(RING - 2) * DPW>();
             else --ready;
             __syncthreads();
-            issue(dc, slot == 0 ? RING - 1 : slot - 1);
-            dc.next(p);
+            issue(dc, dbase, slot == 0 ? RING - 1 : slot - 1);
+            advance(dc, dbase);
             block(slot);
             slot = slot == RING - 1 ? 0 : slot + 1;
         } while (++cc.blk < cc.nblk);
