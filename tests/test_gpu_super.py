@@ -165,6 +165,42 @@ def test_super_stream_accumulates(oracle_mod):
     st.close()
 
 
+def test_super_f6_without_workspace_falls_back(oracle_mod):
+    """The stream and batch entry points hold no fp6 workspace: a 4-bit fp6 job that plans
+    super-tiles (512 inputs) runs 128-tiles there and still gives the oracle's bits."""
+    import torch
+
+    from paper_1107_4264_amd import xcorr as X
+    from tests.gpu_util import device
+
+    dev = device()
+    ns, npol, F, chunk, nchunk = 256, 2, 2, 40, 2
+    assert X.xcorr_plan(ns, npol, F, chunk, X.IN_CI4, X.ACC_F6E3M2_MMA_F32, 0)["tile"] == 512
+    v = synth.voltages_np(synth.SEED_BASE + 69, chunk * nchunk, F, ns * npol, ("uniform", -8, 7))
+    packed = synth.pack_ci4(v)
+    want = oracle_mod.xcorr(packed, ns, npol, fmt=oracle_mod.CI4)
+    say("super f6 stream fallback")
+    st = X.Stream(ns, npol, F, chunk, "ci4", "f6")
+    chunks = [torch.from_numpy(np.ascontiguousarray(packed[c * chunk:(c + 1) * chunk])).pin_memory()
+              for c in range(nchunk)]
+    out = st.begin()
+    for c in range(nchunk):
+        st.push(chunks[c])
+    assert st.end() == chunk * nchunk
+    torch.cuda.synchronize()
+    _check(out.cpu().numpy(), want, "super-f6-stream")
+    st.close()
+    say("super f6 batch fallback")
+    first = np.ascontiguousarray(packed[:chunk])
+    b = X.Batch([(ns, npol, F, chunk), (20, 2, 1, 33)], "ci4", "f6")
+    small = synth.pack_ci4(synth.voltages_np(synth.SEED_BASE + 70, 33, 1, 40, ("uniform", -8, 7)))
+    outs = b.run([torch.from_numpy(first).to(dev), torch.from_numpy(small).to(dev)])
+    torch.cuda.synchronize()
+    _check(outs[0].cpu().numpy(), oracle_mod.xcorr(first, ns, npol, fmt=oracle_mod.CI4), "super-f6-batch/0")
+    _check(outs[1].cpu().numpy(), oracle_mod.xcorr(small, 20, 2, fmt=oracle_mod.CI4), "super-f6-batch/1")
+    b.close()
+
+
 def test_super_misaligned_input_falls_back(oracle_mod):
     """An input pointer off the 16-byte grid runs 128-tiles (the row copies need aligned
     rows) and still gives the oracle's bits."""
