@@ -129,6 +129,12 @@ struct SCursor {
     {
         if (++blk == nblk) set(p, step + 1);
     }
+    // two blocks at a time (the second may lie past the item's last block)
+    __device__ __forceinline__ void next2(const XJob &p)
+    {
+        blk += 2;
+        if (blk >= nblk) set(p, step + 1);
+    }
 };
 
 // Byte address of input 0 in the first row of the block the cursor points at.
@@ -532,7 +538,7 @@ int launch_super_pair(const XJob &job, int cus, hipStream_t stream)
 
 constexpr int F6_UNIT = 48;    // bytes per input per block
 constexpr int F6_CT = 512;     // threads per workgroup: eight waves, two per SIMD
-constexpr int F6_RING = 6;     // blocks in the LDS ring (measured: 8 is no faster)
+constexpr int F6_RING = 3;     // slots in the LDS ring, two blocks each
 
 // fp16 high bytes of four signed 4-bit values (one per byte, low nibble; the low bytes of
 // these fp16 values are zero): byte tables of the values 0..7 and -8..-1 indexed by the
@@ -631,8 +637,9 @@ __global__ __launch_bounds__(256) void f6_pack_kernel(const uint8_t *__restrict_
 template <int TRI>
 struct F6Geo {
     static constexpr int ROWB = 256 * F6_UNIT, COLB = TRI ? 0 : 128 * F6_UNIT;
-    static constexpr int SLOT = ROWB + COLB, NCOPY = SLOT / 1024, LDS = F6_RING * SLOT;
-    static_assert(SLOT % 1024 == 0 && LDS <= 160 * 1024, "whole copies and LDS budget");
+    static constexpr int SUB = ROWB + COLB, SUBC = SUB / 1024;  // one block, its copies
+    static constexpr int SLOT = 2 * SUB, NCOPY = 2 * SUBC, LDS = F6_RING * SLOT;
+    static_assert(SUB % 1024 == 0 && LDS <= 160 * 1024, "whole copies and LDS budget");
 };
 
 // Triangle block i (0..8) of SIMD s: the nine blocks below the diagonal in block rows s and
@@ -748,8 +755,8 @@ __device__ __forceinline__ void run_wave_f6(const XJob &p, int lane)
         return (uint64_t)p.work + (uint64_t)((int64_t)c.f * ntb + tb) * blk_bytes;
     };
     auto advance = [&](SCursor<TRI> &c, uint64_t &bbase) __attribute__((always_inline)) {
-        c.next(p);
-        bbase = c.blk == 0 ? block_base_f6(c) : bbase + blk_bytes;
+        c.next2(p);
+        bbase = c.blk == 0 ? block_base_f6(c) : bbase + 2 * blk_bytes;
     };
     // descriptor of one segment of that block (nothing past the end)
     auto desc = [&](uint64_t bbase, bool valid, int first, int bytes) __attribute__((always_inline)) {
@@ -761,14 +768,20 @@ __device__ __forceinline__ void run_wave_f6(const XJob &p, int lane)
         r[3] = 0x00020000;
         return r;
     };
+    // the two blocks of a slot: the cursor's block and the next one (zeros past the item)
     auto issue = [&](const SCursor<TRI> &c, uint64_t bbase, int slot) __attribute__((always_inline)) {
         const uint32_t sb = lds0 + (uint32_t)(slot * G::SLOT);
-        const i32x4s dr = desc(bbase, c.valid, c.seg_a, G::ROWB);
-        const i32x4s dcol = desc(bbase, c.valid, TRI ? c.seg_a : c.seg_b, TRI ? G::ROWB : G::COLB);
+        const bool v1 = c.valid && c.blk + 1 < c.nblk;
+        const i32x4s dr0 = desc(bbase, c.valid, c.seg_a, G::ROWB);
+        const i32x4s dc0 = desc(bbase, c.valid, TRI ? c.seg_a : c.seg_b, TRI ? G::ROWB : G::COLB);
+        const i32x4s dr1 = desc(bbase + blk_bytes, v1, c.seg_a, G::ROWB);
+        const i32x4s dc1 = desc(bbase + blk_bytes, v1, TRI ? c.seg_a : c.seg_b, TRI ? G::ROWB : G::COLB);
         static_for<DPW>([&](auto M) __attribute__((always_inline)) {
             constexpr int k = W + 8 * decltype(M)::value;
-            if constexpr (k < 12) dma16(dr, sb + 1024 * k, (uint32_t)(1024 * k + 16 * lane));
-            else dma16(dcol, sb + 1024 * k, (uint32_t)(1024 * (k - 12) + 16 * lane));
+            constexpr int h = k / G::SUBC, kk = k % G::SUBC;
+            const uint32_t dst = sb + (uint32_t)(h * G::SUB + 1024 * kk);
+            if constexpr (kk < 12) dma16(h ? dr1 : dr0, dst, (uint32_t)(1024 * kk + 16 * lane));
+            else dma16(h ? dc1 : dc0, dst, (uint32_t)(1024 * (kk - 12) + 16 * lane));
         });
     };
 
@@ -779,8 +792,8 @@ __device__ __forceinline__ void run_wave_f6(const XJob &p, int lane)
         aim[b] = (f32x16){};
     }
     F6Frag P[16], R[8];
-    auto block = [&](int slot) __attribute__((always_inline)) {
-        const uint32_t sb = lds0 + (uint32_t)(slot * G::SLOT);
+    auto block = [&](int slot, int h) __attribute__((always_inline)) {
+        const uint32_t sb = lds0 + (uint32_t)(slot * G::SLOT + h * G::SUB);
         static_for<16>([&](auto F) __attribute__((always_inline)) {
             constexpr int f = decltype(F)::value;
             if constexpr (S::reads(f))
@@ -840,10 +853,11 @@ __device__ __forceinline__ void run_wave_f6(const XJob &p, int lane)
     }
     wait_vm<(RING - 2) * DPW>();
     int slot = 0, ready = 1;
-    // items, each a loop over its blocks, then its stores.  A block: its copies complete
-    // (own, then everyone's: the barrier also means that every wave has issued the MFMAs of
-    // the previous block, so that block's slot is free); the copy of block + RING - 1 into
-    // that slot; this block's fragments and MFMAs.
+    // items, each a loop over its blocks two at a time (one ring slot; past the item's last
+    // block the slot holds zeros), then its stores.  A slot: its copies complete (own, then
+    // everyone's: the barrier also means that every wave has issued the MFMAs of the
+    // previous slot, so that slot is free); the copy of slot + RING - 1 into it; this
+    // slot's fragments and MFMAs.
     while (cc.valid) {
         do {
             if (ready == 0) wait_vm<(RING - 2) * DPW>();
@@ -851,9 +865,10 @@ __device__ __forceinline__ void run_wave_f6(const XJob &p, int lane)
             __syncthreads();
             issue(dc, dbase, slot == 0 ? RING - 1 : slot - 1);
             advance(dc, dbase);
-            block(slot);
+            block(slot, 0);
+            block(slot, 1);
             slot = slot == RING - 1 ? 0 : slot + 1;
-        } while (++cc.blk < cc.nblk);
+        } while ((cc.blk += 2) < cc.nblk);
         wait_vm<0>();
         ready = RING - 1;
         store(cc);
