@@ -531,7 +531,9 @@ int launch_super_pair(const XJob &job, int cus, hipStream_t stream)
 // zeros to whole super-rows and the last block's samples past ntime zero, so that a piece
 // copies contiguous segments (12 KiB for 256 row inputs, 6 KiB for 128 column inputs)
 // straight into LDS: the main kernel converts nothing.  Eight waves, two per SIMD, with
-// 2 x 2 blocks each in a rectangle and four or five blocks of a SIMD's nine in a triangle.
+// 2 x 2 blocks each in a rectangle and four or five blocks of a SIMD's nine in a triangle;
+// two blocks share a ring slot and its barrier (8 % faster rectangles than one; an
+// eight-block ring of single blocks was no faster than six).
 // Measured and dropped: four waves with 2 x 4 blocks (their 256 accumulator registers
 // spill), and the next block's fragments read during this block's MFMAs (no faster: the
 // pieces are bound by LDS bandwidth, not by the reads' latency).
