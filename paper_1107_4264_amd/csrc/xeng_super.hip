@@ -129,10 +129,10 @@ struct SCursor {
     {
         if (++blk == nblk) set(p, step + 1);
     }
-    // two blocks at a time (the second may lie past the item's last block)
-    __device__ __forceinline__ void next2(const XJob &p)
+    // n blocks at a time (the later ones may lie past the item's last block)
+    __device__ __forceinline__ void next_n(const XJob &p, int n)
     {
-        blk += 2;
+        blk += n;
         if (blk >= nblk) set(p, step + 1);
     }
 };
@@ -532,15 +532,17 @@ int launch_super_pair(const XJob &job, int cus, hipStream_t stream)
 // copies contiguous segments (12 KiB for 256 row inputs, 6 KiB for 128 column inputs)
 // straight into LDS: the main kernel converts nothing.  Eight waves, two per SIMD, with
 // 2 x 2 blocks each in a rectangle and four or five blocks of a SIMD's nine in a triangle;
-// two blocks share a ring slot and its barrier (8 % faster rectangles than one; an
-// eight-block ring of single blocks was no faster than six).
+// four blocks share a ring slot and its barrier, two slots (two blocks per slot: 8 %
+// faster rectangles than one; four: another 1-3 %; an eight-block ring of single blocks
+// was no faster than six).
 // Measured and dropped: four waves with 2 x 4 blocks (their 256 accumulator registers
 // spill), and the next block's fragments read during this block's MFMAs (no faster: the
 // pieces are bound by LDS bandwidth, not by the reads' latency).
 
 constexpr int F6_UNIT = 48;    // bytes per input per block
 constexpr int F6_CT = 512;     // threads per workgroup: eight waves, two per SIMD
-constexpr int F6_RING = 3;     // slots in the LDS ring, two blocks each
+constexpr int F6_NSUB = 4;     // 32-sample blocks per LDS ring slot (one barrier each)
+constexpr int F6_RING = F6_NSUB == 2 ? 3 : 2;  // slots in the LDS ring
 
 // fp16 high bytes of four signed 4-bit values (one per byte, low nibble; the low bytes of
 // these fp16 values are zero): byte tables of the values 0..7 and -8..-1 indexed by the
@@ -640,7 +642,7 @@ template <int TRI>
 struct F6Geo {
     static constexpr int ROWB = 256 * F6_UNIT, COLB = TRI ? 0 : 128 * F6_UNIT;
     static constexpr int SUB = ROWB + COLB, SUBC = SUB / 1024;  // one block, its copies
-    static constexpr int SLOT = 2 * SUB, NCOPY = 2 * SUBC, LDS = F6_RING * SLOT;
+    static constexpr int SLOT = F6_NSUB * SUB, NCOPY = F6_NSUB * SUBC, LDS = F6_RING * SLOT;
     static_assert(SUB % 1024 == 0 && LDS <= 160 * 1024, "whole copies and LDS budget");
 };
 
@@ -757,8 +759,8 @@ __device__ __forceinline__ void run_wave_f6(const XJob &p, int lane)
         return (uint64_t)p.work + (uint64_t)((int64_t)c.f * ntb + tb) * blk_bytes;
     };
     auto advance = [&](SCursor<TRI> &c, uint64_t &bbase) __attribute__((always_inline)) {
-        c.next2(p);
-        bbase = c.blk == 0 ? block_base_f6(c) : bbase + 2 * blk_bytes;
+        c.next_n(p, F6_NSUB);
+        bbase = c.blk == 0 ? block_base_f6(c) : bbase + F6_NSUB * blk_bytes;
     };
     // descriptor of one segment of that block (nothing past the end)
     auto desc = [&](uint64_t bbase, bool valid, int first, int bytes) __attribute__((always_inline)) {
@@ -770,20 +772,20 @@ __device__ __forceinline__ void run_wave_f6(const XJob &p, int lane)
         r[3] = 0x00020000;
         return r;
     };
-    // the two blocks of a slot: the cursor's block and the next one (zeros past the item)
+    // the F6_NSUB blocks of a slot: the cursor's block and the following ones (zeros past
+    // the item)
     auto issue = [&](const SCursor<TRI> &c, uint64_t bbase, int slot) __attribute__((always_inline)) {
         const uint32_t sb = lds0 + (uint32_t)(slot * G::SLOT);
-        const bool v1 = c.valid && c.blk + 1 < c.nblk;
-        const i32x4s dr0 = desc(bbase, c.valid, c.seg_a, G::ROWB);
-        const i32x4s dc0 = desc(bbase, c.valid, TRI ? c.seg_a : c.seg_b, TRI ? G::ROWB : G::COLB);
-        const i32x4s dr1 = desc(bbase + blk_bytes, v1, c.seg_a, G::ROWB);
-        const i32x4s dc1 = desc(bbase + blk_bytes, v1, TRI ? c.seg_a : c.seg_b, TRI ? G::ROWB : G::COLB);
         static_for<DPW>([&](auto M) __attribute__((always_inline)) {
             constexpr int k = W + 8 * decltype(M)::value;
             constexpr int h = k / G::SUBC, kk = k % G::SUBC;
+            const bool v = c.valid && c.blk + h < c.nblk;
             const uint32_t dst = sb + (uint32_t)(h * G::SUB + 1024 * kk);
-            if constexpr (kk < 12) dma16(h ? dr1 : dr0, dst, (uint32_t)(1024 * kk + 16 * lane));
-            else dma16(h ? dc1 : dc0, dst, (uint32_t)(1024 * (kk - 12) + 16 * lane));
+            if constexpr (kk < 12)
+                dma16(desc(bbase + h * blk_bytes, v, c.seg_a, G::ROWB), dst, (uint32_t)(1024 * kk + 16 * lane));
+            else
+                dma16(desc(bbase + h * blk_bytes, v, TRI ? c.seg_a : c.seg_b, TRI ? G::ROWB : G::COLB), dst,
+                      (uint32_t)(1024 * (kk - 12) + 16 * lane));
         });
     };
 
@@ -867,10 +869,9 @@ __device__ __forceinline__ void run_wave_f6(const XJob &p, int lane)
             __syncthreads();
             issue(dc, dbase, slot == 0 ? RING - 1 : slot - 1);
             advance(dc, dbase);
-            block(slot, 0);
-            block(slot, 1);
+            static_for<F6_NSUB>([&](auto H) __attribute__((always_inline)) { block(slot, decltype(H)::value); });
             slot = slot == RING - 1 ? 0 : slot + 1;
-        } while ((cc.blk += 2) < cc.nblk);
+        } while ((cc.blk += F6_NSUB) < cc.nblk);
         wait_vm<0>();
         ready = RING - 1;
         store(cc);
